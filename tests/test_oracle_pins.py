@@ -1,0 +1,410 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: closed-form
+1-D integrals, null spaces of the differential operators, conservation sums,
+library direct solvers, the exact plane-wave solution of an empty box, and
+the unknown counts the paper prints.  A plausible slip in the oracle (dropped
+term, wrong sign, transposed index) fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fem, solve
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------- closed forms
+def _m1(a, b, h):
+    return h / 6.0 * (2.0 if a == b else 1.0)
+
+
+def _k1(a, b, h):
+    return (1.0 if a == b else -1.0) / h
+
+
+def _g1(a):
+    # int N_a' N_b over [0, h] = -1/2 (a = 0) or +1/2 (a = 1), any b
+    return -0.5 if a == 0 else 0.5
+
+
+def _kron_tables(h):
+    L = fem.LOCAL_NODES
+    G = np.zeros((3, 3, 8, 8))
+    M = np.zeros((8, 8))
+    for a in range(8):
+        for b in range(8):
+            M[a, b] = np.prod([_m1(L[a, t], L[b, t], h[t]) for t in range(3)])
+            for p in range(3):
+                for q in range(3):
+                    v = 1.0
+                    for t in range(3):
+                        if t == p and t == q:
+                            v *= _k1(L[a, t], L[b, t], h[t])
+                        elif t == p:
+                            v *= _g1(L[a, t])
+                        elif t == q:
+                            v *= _g1(L[b, t])
+                        else:
+                            v *= _m1(L[a, t], L[b, t], h[t])
+                    G[p, q, a, b] = v
+    return G, M
+
+
+@pytest.mark.parametrize("h", [(0.1, 0.1, 0.1), (0.1, 0.2, 0.35), (1.0, 0.5, 2.0)])
+def test_element_tables_match_kronecker_closed_form(h):
+    """2x2x2 Gauss is exact for these integrands, so the quadrature tables
+    must equal the Kronecker products of the 1-D mass/stiffness/mixed
+    integrals:  curl-curl = delta_ij sum_m G_mm - G_ji,  div-div = G_ij,
+    mass = delta_ij M."""
+    Kc, Kd, Km = fem.element_matrices(h)
+    G, M = _kron_tables(h)
+    scale = max(abs(Kc).max(), abs(Kd).max())
+    for a in range(8):
+        for b in range(8):
+            for i in range(3):
+                for j in range(3):
+                    kc = (i == j) * sum(G[m, m, a, b] for m in range(3)) - G[j, i, a, b]
+                    assert abs(Kc[3 * a + i, 3 * b + j] - kc) <= 1e-14 * scale
+                    assert abs(Kd[3 * a + i, 3 * b + j] - G[i, j, a, b]) <= 1e-14 * scale
+                    assert abs(Km[3 * a + i, 3 * b + j] - (i == j) * M[a, b]) <= 1e-15 * abs(Km).max()
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_face_tables_match_closed_form(axis):
+    h = (0.1, 0.2, 0.3)
+    Mf, Sf = fem.face_matrices(axis, h)
+    t1, t2 = [t for t in range(3) if t != axis]
+    L = fem.LOCAL_NODES[fem.face_local_nodes(axis, 0)]
+    for a in range(4):
+        for b in range(4):
+            m = _m1(L[a, t1], L[b, t1], h[t1]) * _m1(L[a, t2], L[b, t2], h[t2])
+            s = (_k1(L[a, t1], L[b, t1], h[t1]) * _m1(L[a, t2], L[b, t2], h[t2])
+                 + _m1(L[a, t1], L[b, t1], h[t1]) * _k1(L[a, t2], L[b, t2], h[t2]))
+            assert abs(Mf[a, b] - m) <= 1e-16
+            assert abs(Sf[a, b] - s) <= 1e-14 * abs(Sf).max()
+    # tangential stiffness annihilates constants; face mass sums to the area
+    assert abs(Sf.sum(axis=1)).max() <= 1e-14 * abs(Sf).max()
+    assert abs(Mf.sum() - h[t1] * h[t2]) <= 1e-16
+
+
+# ------------------------------------------------------------------ invariants
+def _with(prob, **kw):
+    import copy
+    q = copy.deepcopy(prob)
+    for k, v in kw.items():
+        setattr(q, k, v)
+    return q
+
+
+def _field(mesh, fn):
+    X = mesh.node_coords()
+    return np.stack(fn(X[:, 0], X[:, 1], X[:, 2]), axis=1).astype(np.complex128).ravel()
+
+
+def test_matrix_is_complex_symmetric():
+    """Invariant (a): A = A^T (plain transpose), with lossy random eps/mu,
+    PEC elements and ABC faces."""
+    rng = np.random.default_rng(1)
+    p = W.random_small(rng, n=(4, 3, 5), n_pec=3, lossy=True)
+    p.mu_r[:] = rng.uniform(1.0, 2.0, size=p.mu_r.shape)
+    A = fem.assemble(p)
+    assert abs(A - A.T).max() <= 1e-14 * abs(A).max()
+    # and it is not Hermitian: the ABC and the loss make it complex
+    assert abs(A - A.conj().T).max() > 1e-3 * abs(A).max()
+
+
+def test_curl_and_penalty_null_spaces():
+    """Invariant (b): the volume curl-curl + penalty part annihilates constant
+    fields; the curl part alone annihilates gradient fields that the
+    trilinear space represents exactly; the penalty part alone annihilates
+    divergence-free fields represented exactly.  Heterogeneous eps and PEC
+    holes must not matter."""
+    rng = np.random.default_rng(2)
+    p = W.random_small(rng, n=(4, 4, 4), n_pec=2, lossy=True,
+                       faces=(W.FACE_NATURAL,) * 6)
+    p.origin = (0.3, -0.2, 0.1)
+    mesh = fem.Mesh(p)
+    K = fem.assemble(_with(p, k0=0.0, penalty_s=1.0))        # curl + penalty
+    C = fem.assemble(_with(p, k0=0.0, penalty_s=0.0))        # curl only
+    P = K - C                                                # penalty only
+    scale = abs(K).max()
+    for c in range(3):
+        e = np.zeros(mesh.n_unknowns, np.complex128)
+        e[c::3] = 1.0
+        assert abs(K @ e).max() <= 1e-13 * scale
+    grads = [lambda x, y, z: (np.ones_like(x), 0 * x, 0 * x),
+             lambda x, y, z: (y, x, 0 * x),                 # grad(xy)
+             lambda x, y, z: (y * z, x * z, x * y),         # grad(xyz)
+             lambda x, y, z: (2 * x, 2 * y, 0 * z)]         # grad(x^2 + y^2)
+    for g in grads:
+        v = _field(mesh, g)
+        assert abs(C @ v).max() <= 1e-12 * scale * abs(v).max()
+    divfree = [lambda x, y, z: (y, z, x),
+               lambda x, y, z: (y * z, x * z, 0 * z),       # div = 0
+               lambda x, y, z: (z, 0 * x, y)]
+    for g in divfree:
+        v = _field(mesh, g)
+        assert abs(P @ v).max() <= 1e-12 * scale * abs(v).max()
+    # the curl part does NOT annihilate a rotational field: guards against a
+    # vanished operator passing the checks above
+    v = _field(mesh, lambda x, y, z: (-y, x, 0 * z))
+    assert abs(C @ v).max() > 1e-3 * scale * abs(v).max()
+
+
+def test_mass_sums_to_volume():
+    """Invariant (c): for each component the k0^2 mu mass part sums to
+    k0^2 * sum_e mu_e V_e over the active elements."""
+    rng = np.random.default_rng(3)
+    p = W.random_small(rng, n=(3, 4, 2), n_pec=2, faces=(W.FACE_NATURAL,) * 6,
+                       h=(0.1, 0.15, 0.2))
+    p.mu_r[:] = rng.uniform(1.0, 3.0, size=p.mu_r.shape) + 0.1j
+    k0 = 2.7
+    Mk = fem.assemble(_with(p, k0=0.0)) - fem.assemble(_with(p, k0=k0))   # = k0^2 mu M
+    V = p.h[0] * p.h[1] * p.h[2]
+    expected = k0 ** 2 * V * p.mu_r[p.pec == 0].sum()
+    for c in range(3):
+        sub = Mk[c::3, :][:, c::3]
+        assert abs(sub.sum() - expected) <= 1e-13 * abs(expected)
+        # no coupling between different components
+        other = Mk[c::3, :][:, (c + 1) % 3::3]
+        assert abs(other).max() <= 1e-16 * abs(expected)
+
+
+def test_interior_stencil_closed_form():
+    """Free space, s = 1, eps = mu = 1: curl-curl + grad-div is the vector
+    Laplacian, so an interior block row is diagonal and each component sees
+    the Kronecker stencil  K(x)M(x)M + M(x)K(x)M + M(x)M(x)K - k0^2 M(x)M(x)M
+    with 1-D K = (1/h) [-1, 2, -1] and M = (h/6) [1, 4, 1]."""
+    n = 4
+    p, _ = W.free_cube(n, wavelengths=0.4)
+    h = p.h[0]
+    k0 = p.k0
+    p.faces = (W.FACE_NATURAL,) * 6
+    A = fem.assemble(p)
+    mesh = fem.Mesh(p)
+    K1 = {-1: -1 / h, 0: 2 / h, 1: -1 / h}
+    M1 = {-1: h / 6, 0: 4 * h / 6, 1: h / 6}
+    i0 = j0 = k0i = 2
+    a = mesh.node_id[k0i, j0, i0]
+    centre = None
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                b = mesh.node_id[k0i + dz, j0 + dy, i0 + dx]
+                val = (K1[dx] * M1[dy] * M1[dz] + M1[dx] * K1[dy] * M1[dz]
+                       + M1[dx] * M1[dy] * K1[dz] - k0 ** 2 * M1[dx] * M1[dy] * M1[dz])
+                blk = A[3 * a:3 * a + 3, 3 * b:3 * b + 3].toarray()
+                assert np.allclose(blk, val * np.eye(3), rtol=0, atol=1e-14 * 3 / h)
+                if dx == dy == dz == 0:
+                    centre = blk[0, 0]
+    assert abs(centre - (8 * h / 3 - k0 ** 2 * 8 * h ** 3 / 27)) <= 1e-14 * 8 * h / 3
+    # one scalar row touches 27 nodes, one component each (other stored
+    # entries of the 3x3 blocks cancel to rounding)
+    row = A[3 * a].toarray().ravel()
+    assert (abs(row) > 1e-12 / h).sum() == 27
+
+
+def test_abc_row_sums():
+    """The ABC adds j k0 Mf + (j / 2 k0) Sf on the tangential components
+    only.  Sf annihilates constants, so each tangential row sum of the
+    added part is j k0 times the node's share of face area (h^2 / 4 per
+    incident quad); the normal component gets nothing."""
+    n = 3
+    p, _ = W.free_cube(n)
+    h = p.h[0]
+    base = fem.assemble(_with(p, faces=(W.FACE_NATURAL,) * 6))
+    for f in range(6):
+        faces = [W.FACE_NATURAL] * 6
+        faces[f] = W.FACE_ABC
+        D = fem.assemble(_with(p, faces=tuple(faces))) - base
+        axis, side = fem.FACES[f]
+        mesh = fem.Mesh(p)
+        idx = [slice(None)] * 3
+        idx[2 - axis] = 0 if side == 0 else -1            # node_id is (z, y, x)
+        face_nodes = mesh.node_id[tuple(idx)]
+        counts = np.zeros(face_nodes.shape)
+        # number of face quads incident to each face node
+        for t in range(2):
+            sl = [slice(None)] * 2
+            for u in range(2):
+                s2 = [slice(0, -1), slice(0, -1)]
+                s2[0] = slice(t, counts.shape[0] - 1 + t)
+                s2[1] = slice(u, counts.shape[1] - 1 + u)
+                counts[tuple(s2)] += 1
+        for c in range(3):
+            rows = 3 * face_nodes.ravel() + c
+            rs = np.asarray(D[rows, :].sum(axis=1)).ravel()
+            if c == axis:
+                assert abs(rs).max() == 0.0
+                assert D[rows, :].nnz == 0 or abs(D[rows, :]).max() == 0.0
+            else:
+                assert np.allclose(rs, 1j * p.k0 * counts.ravel() * h * h / 4, rtol=1e-13, atol=0)
+        interior = np.setdiff1d(np.arange(mesh.n_nodes), face_nodes.ravel())
+        assert abs(D[np.concatenate([3 * interior + c for c in range(3)]), :]).max() == 0.0
+        # diagonal of a node inside the face (4 quads): face mass 4 (h/3)^2,
+        # tangential stiffness 4 * 2/3; coefficients j k0 and + j / (2 k0) of eq. (3)
+        a = face_nodes[1, 1]
+        t = [u for u in range(3) if u != axis][0]
+        want = 1j * p.k0 * 4 * h * h / 9 + (1j / (2 * p.k0)) * 4 * (2.0 / 3.0)
+        assert abs(D[3 * a + t, 3 * a + t] - want) <= 1e-14 * abs(want)
+
+
+def test_rhs_normal_incidence_closed_form():
+    """Wave along +z, polarised along x, ABC box.  On the -z face (incoming)
+    n x curl H_i = -j k0 H_i, so interior nodes of that face get
+    b_x = 2 j k0 (4 h^2 / 4); on the +z face (outgoing) g(H_i) equals
+    n x curl H_i and b = 0; nodes off the boundary get 0."""
+    n = 4
+    p, waves = W.free_cube(n)
+    h = p.h[0]
+    b = fem.rhs(p, waves)[:, 0].reshape(-1, 3)
+    mesh = fem.Mesh(p)
+    inner = mesh.node_id[0, 1:-1, 1:-1].ravel()
+    assert np.allclose(b[inner, 0], 2j * p.k0 * h * h, rtol=1e-14, atol=0)
+    assert abs(b[inner, 1:]).max() == 0.0
+    outer = mesh.node_id[-1, 1:-1, 1:-1].ravel()
+    assert abs(b[outer]).max() <= 1e-14 * p.k0 * h * h
+    interior = mesh.node_id[1:-1, 1:-1, 1:-1].ravel()
+    assert abs(b[interior]).max() == 0.0
+
+
+def test_rhs_side_face_sums():
+    """Same wave; on the +x face (n = +x), -(n x curl H_i)_z = j k0 H_x, the
+    tangential field H_y = H_z = 0, so the z-rows of that face sum to
+    j k0 int exp(-j k0 z) dS (partition of unity).  Compared with the exact
+    integral within the 2-point Gauss error."""
+    p, waves = W.free_cube(7, wavelengths=0.7)   # the integral is not zero
+    p.faces = (W.FACE_NATURAL, W.FACE_ABC) + (W.FACE_NATURAL,) * 4
+    b = fem.rhs(p, waves)[:, 0].reshape(-1, 3)
+    mesh = fem.Mesh(p)
+    L = p.nz * p.h[2]
+    Ly = p.ny * p.h[1]
+    face = mesh.node_id[:, :, -1].ravel()
+    exact = 1j * p.k0 * Ly * (1 - np.exp(-1j * p.k0 * L)) / (1j * p.k0)
+    got = b[face, 2].sum()
+    assert abs(got - exact) <= 1e-3 * abs(exact)
+    assert abs(b[face, :2]).max() == 0.0
+
+
+# ------------------------------------------------------------------ the solve
+@pytest.mark.parametrize("n", [(2, 2, 2), (3, 3, 3), (4, 3, 4)])
+def test_dense_sparse_cocg_agree(n):
+    """Invariant (d): LAPACK LU, SuperLU and COCG-Jacobi give the same
+    solution on tiny random meshes with one PEC element."""
+    rng = np.random.default_rng(sum(n))
+    p = W.random_small(rng, n=n, n_pec=1, lossy=False)
+    waves = [W.random_wave(rng) for _ in range(2)]
+    A = fem.assemble(p)
+    B = fem.rhs(p, waves)
+    x_dense = solve.dense_solve(A, B)
+    x_sparse = solve.sparse_solve(A, B)
+    assert np.linalg.norm(x_dense - x_sparse) <= 1e-12 * np.linalg.norm(x_dense)
+    for r in range(2):
+        res = solve.cocg(A, B[:, r], rtol=1e-14, maxiter=5000)
+        assert not res.breakdown
+        assert solve.residual(A, res.x, B[:, r]) <= 1e-13
+        assert np.linalg.norm(res.x - x_dense[:, r]) <= 1e-10 * np.linalg.norm(x_dense[:, r])
+
+
+def test_empty_box_reproduces_incident_wave():
+    """Invariant (e): with no scatterer the total field is the incident
+    plane wave.  The nodal error is a few percent at 10 nodes per
+    wavelength and falls about 4x (second order) when h halves.  The
+    opposite right-hand-side sign gives an O(1) error."""
+    errs = []
+    for n in (10, 20):
+        p, waves = W.free_cube(n)
+        A = fem.assemble(p)
+        b = fem.rhs(p, waves)[:, 0]
+        res = solve.cocg(A, b, rtol=1e-11, maxiter=5000)
+        hi = fem.incident_field(waves[0], fem.Mesh(p).node_coords(), p.k0).ravel()
+        errs.append(np.linalg.norm(res.x - hi) / np.linalg.norm(hi))
+        if n == 10:
+            wrong = solve.cocg(A, -b, rtol=1e-11, maxiter=5000)
+            assert np.linalg.norm(wrong.x - hi) / np.linalg.norm(hi) > 1.0
+    assert 0.01 < errs[0] < 0.1
+    assert errs[0] / errs[1] > 3.0
+
+
+def test_oblique_wave_in_lossy_free_box_converges():
+    """The empty-box property must hold for any direction/polarisation (all
+    six faces then carry incoming and outgoing parts) and for mesh sizes that
+    are not a whole number of wavelengths."""
+    rng = np.random.default_rng(5)
+    wave = W.random_wave(rng)
+    errs = []
+    for n in (7, 14):
+        p, _ = W.free_cube(n, wavelengths=0.7)
+        A = fem.assemble(p)
+        b = fem.rhs(p, [wave])[:, 0]
+        x = solve.cocg(A, b, rtol=1e-11, maxiter=5000).x
+        hi = fem.incident_field(wave, fem.Mesh(p).node_coords(), p.k0).ravel()
+        errs.append(np.linalg.norm(x - hi) / np.linalg.norm(hi))
+    assert errs[0] < 0.1 and errs[0] / errs[1] > 3.0
+
+
+def test_cocg_breakdown_detected():
+    """b with b^T D^-1 b = 0 makes rho_0 = 0: COCG must report breakdown."""
+    p, _ = W.free_cube(3)
+    A = fem.assemble(p)
+    D = A.diagonal()
+    v = np.zeros(A.shape[0], np.complex128)
+    v[0], v[1] = 1.0, 1.0j
+    b = v * np.sqrt(D)
+    assert abs(solve.bilinear(b, b / D)) < 1e-15
+    res = solve.cocg(A, b, rtol=1e-10, maxiter=100)
+    assert res.breakdown and res.iters == 0
+
+
+# ----------------------------------------------------------- bookkeeping pins
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(HERE, "golden", name)) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append([int(t) for t in line.split()[:2]])
+    return rows
+
+
+def test_unknown_counts_match_paper():
+    """Three complex unknowns per node, six real degrees of freedom per node:
+    the paper's printed counts (section 1, figure 3, section 3.2)."""
+    rows = _golden_rows("paper_sizes.txt")
+    nodes_per_side, unknowns = rows[0]
+    m = nodes_per_side - 1
+    p = W._blank(m, m, m, (0.1,) * 3, (0, 0, 0), 2 * math.pi)
+    assert fem.Mesh(p).n_unknowns == unknowns
+    for nodes, dof in rows[1:]:
+        assert 2 * 3 * nodes == dof
+
+
+def test_pec_removes_only_interior_nodes():
+    """PEC elements are removed; nodes on the PEC surface stay active."""
+    p, _ = W.pec_cube(30)
+    mesh = fem.Mesh(p)
+    assert int(p.pec.sum()) == 1000
+    assert mesh.n_nodes == 31 ** 3 - 9 ** 3
+
+
+def test_row_sampler_matches_global_assembly():
+    """The one-row-at-a-time assembly used to check huge problems agrees
+    with the global COO assembly on a small random problem."""
+    rng = np.random.default_rng(7)
+    p = W.random_small(rng, n=(4, 3, 3), n_pec=3, lossy=True)
+    p.mu_r[:] = 1.0 + rng.uniform(0, 1, size=p.mu_r.shape)
+    A = fem.assemble(p)
+    mesh = fem.Mesh(p)
+    nodes = rng.choice(mesh.n_nodes, size=12, replace=False)
+    rows = fem.assemble_rows(p, nodes)
+    for a in nodes:
+        full = A[3 * a:3 * a + 3].toarray()
+        got = np.zeros_like(full)
+        for b, blk in rows[a].items():
+            got[:, 3 * b:3 * b + 3] = blk
+        assert np.abs(got - full).max() <= 1e-14 * abs(A).max()
