@@ -1,0 +1,309 @@
+/*
+ * femh.h -- C ABI of the MI355X (gfx950) nodal-hexahedral H-field
+ * finite element scattering solver.
+ *
+ * The method (Vollaire, Nicolas, Nicolas, "Parallel computing for the
+ * finite element method", section 2, eqs. (1)-(4)): the total magnetic
+ * field H of a time-harmonic scattering problem, three complex components
+ * per node of a structured box of first-order (8-node trilinear)
+ * hexahedra, satisfies
+ *
+ *     int (1/eps_r) curl W . curl H + s int div W div H
+ *       - k0^2 int mu_r W . H + int_{S_ext} W . g_ABC(H)
+ *     = int_{S_ext} W . [ g_ABC(H_i) - n x curl H_i ],
+ *
+ * with the second-order Engquist-Majda condition of eq. (3),
+ * g_ABC(H) = j k0 H_t - (j / 2k0) lap_t H_t, on outer faces tagged ABC,
+ * the grad-div penalty of eq. (2) with weight s, and PEC elements removed
+ * (PEC is a natural condition for H).  The discrete system is a
+ * complex-symmetric (A = A^T, not Hermitian) matrix of 3x3 blocks, one
+ * block per pair of nodes sharing an active element, solved by conjugate
+ * gradients with diagonal preconditioning (section 3.1.5), read for a
+ * complex-symmetric matrix as COCG (unconjugated bilinear form).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns a femh_status (0 = success, < 0 = error) unless
+ *     noted.  femh_last_error() returns a message for the calling thread's
+ *     last failing call.
+ *   - Input arrays are copied (or fully consumed) before the call returns;
+ *     the caller may free them afterwards.  Output buffers are owned and
+ *     sized by the caller.
+ *   - "device pointer" means memory of the context's device, readable and
+ *     writable by kernels on the context's stream.
+ *   - Unless a call says it is asynchronous, it returns after its device
+ *     work on the context's stream has completed.
+ *   - Handles own their device memory; destroy(NULL) is a no-op.
+ *   - One context (and its problems) must not be used by two threads at
+ *     once.  The server calls are the exception: they are thread-safe.
+ *   - Element arrays are [nz][ny][nx] (x fastest).  Active nodes are the
+ *     nodes of at least one non-PEC element, numbered in lexicographic grid
+ *     order (x fastest).  Unknown index = 3 * node + component (x, y, z).
+ *   - Complex numbers are interleaved (re, im) pairs: femh_c128 in FP64,
+ *     and pairs of float for complex64 device vectors.
+ */
+#ifndef FEMH_H
+#define FEMH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } femh_c128;
+
+typedef enum {
+  FEMH_OK = 0,
+  FEMH_E_INVALID = -1,        /* bad argument or descriptor */
+  FEMH_E_NONFINITE = -2,      /* NaN/Inf in an input */
+  FEMH_E_OOM = -3,            /* device allocation failed / over budget */
+  FEMH_E_DEVICE = -4,         /* HIP runtime error, or no usable gfx950 device */
+  FEMH_E_NOT_CONVERGED = -5,  /* iteration limit reached; best iterate returned */
+  FEMH_E_BREAKDOWN = -6,      /* COCG breakdown (x^T A x or r^T z vanished) */
+  FEMH_E_CANCELLED = -7,      /* server request cancelled */
+  FEMH_E_PENDING = -8,        /* server request not finished yet */
+  FEMH_E_NOT_FOUND = -9       /* unknown server ticket */
+} femh_status;
+
+/* Outer face tags, faces ordered -x, +x, -y, +y, -z, +z. */
+enum { FEMH_FACE_ABC = 0,      /* eq. (3) absorbing condition */
+       FEMH_FACE_NATURAL = 1   /* no surface term (a PEC wall for H) */ };
+
+typedef enum { FEMH_FP64 = 0,  /* complex128 Krylov solve */
+               FEMH_MIXED = 1  /* complex64 inner COCG, FP64 refinement */ } femh_precision;
+
+typedef enum { FEMH_PRECOND_JACOBI = 0,  /* z = D^-1 r, D = diag(A) (section 3.1.5.1) */
+               FEMH_PRECOND_NONE = 1 } femh_precond;
+
+/* Device memory provider.  alloc returns a device pointer of at least
+ * `bytes` bytes (NULL on failure) usable on the context's stream; free
+ * releases it.  A NULL femh_allocator means hipMalloc/hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} femh_allocator;
+
+/* Problem statement of section 2: a box [origin, origin + (nx hx, ny hy,
+ * nz hz)] of nx*ny*nz hexahedra. */
+typedef struct {
+  int32_t nx, ny, nz;          /* elements per axis, >= 1 */
+  double h[3];                 /* element size per axis, > 0 */
+  double origin[3];            /* minimum corner */
+  const femh_c128* eps_r;      /* [nz][ny][nx] relative permittivity, nonzero; NULL = 1 */
+  const femh_c128* mu_r;       /* [nz][ny][nx] relative permeability; NULL = 1 */
+  const uint8_t* pec;          /* [nz][ny][nx], nonzero = element is PEC (removed); NULL = none */
+  int32_t outer_face[6];       /* FEMH_FACE_* per outer face */
+  double k0;                   /* free-space wavenumber, > 0 */
+  double penalty_s;            /* grad-div penalty weight s >= 0 (eq. (2) gives none); 0 selects 1 */
+  int32_t arrays_on_device;    /* 1: eps_r, mu_r, pec are device pointers, 0: host pointers */
+} femh_problem_desc;
+
+/* Incident plane wave H_i(r) = p exp(-j k0 d . r): |d| = 1, p . d = 0
+ * (within 1e-9).  p is the H polarisation. */
+typedef struct {
+  double d[3];
+  femh_c128 p[3];
+} femh_plane_wave;
+
+/* Solver options; a zero-initialised struct selects the defaults shown. */
+typedef struct {
+  int32_t precision;     /* femh_precision; default FEMH_FP64 */
+  int32_t precond;       /* femh_precond; default Jacobi */
+  double rtol;           /* stop at ||b - A x||_2 <= rtol ||b||_2 (FP64 true residual); default 1e-6 */
+  int32_t max_iter;      /* Krylov iterations in total (inner ones for MIXED); default 50000 */
+  double inner_rtol;     /* MIXED: relative reduction asked of each inner solve; default 1e-5 */
+  int32_t max_outer;     /* MIXED: refinement steps; default 20 */
+  int32_t check_every;   /* iterations queued between host convergence reads; default 32 */
+} femh_solve_opts;
+
+typedef struct {
+  int32_t status;             /* femh_status of this right-hand side */
+  int32_t iters;              /* Krylov iterations (inner ones for MIXED) */
+  int32_t outer_iters;        /* refinement steps (MIXED), restarts (FP64) */
+  int32_t reserved;
+  double rel_residual;        /* final FP64 ||b - A x||_2 / ||b||_2 */
+  double seconds;             /* device time of the solve (HIP events) */
+} femh_solve_stats;
+
+typedef struct {
+  int64_t grid_nodes;         /* (nx+1)(ny+1)(nz+1) */
+  int64_t n_nodes;            /* active nodes (block rows) */
+  int64_t n_unknowns;         /* 3 * n_nodes */
+  int64_t nnzb;               /* stored 3x3 blocks */
+  int64_t device_bytes;       /* device memory held by the problem */
+} femh_problem_info;
+
+typedef struct femh_ctx femh_ctx;
+typedef struct femh_problem femh_problem;
+typedef struct femh_server femh_server;
+
+/* ------------------------------------------------------------ context */
+
+/* Open a context on HIP device `device` (must be gfx950).  `alloc` may be
+ * NULL; `hip_stream` is a hipStream_t to launch on, or NULL for a stream
+ * the context creates (default priority).  *out receives the handle. */
+int femh_ctx_create(int device, const femh_allocator* alloc, void* hip_stream, femh_ctx** out);
+void femh_ctx_destroy(femh_ctx* ctx);
+
+/* Message of the calling thread's last failing call ("" if none).  The
+ * string stays valid until the thread's next femh call. */
+const char* femh_last_error(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int femh_version(void);
+
+/* ------------------------------------------------------ host-only checks */
+
+/* Check a descriptor without touching the device: sizes, finite values,
+ * face tags, eps_r != 0, k0 > 0, s >= 0; host arrays are scanned for
+ * NaN/Inf.  Writes a message into msg[0..n) when it fails. */
+int femh_validate_desc(const femh_problem_desc* desc, char* msg, size_t n);
+
+/* Device bytes a problem plus the vectors of an nrhs-column solve of the
+ * given precision will need.  Exact when the PEC mask is on the host, an
+ * upper bound when it is on the device. */
+int femh_estimate_bytes(const femh_problem_desc* desc, int32_t nrhs, int32_t precision,
+                        int64_t* bytes);
+
+/* Check incident waves: |d| = 1, p . d = 0, finite. */
+int femh_validate_waves(int32_t nrhs, const femh_plane_wave* waves, char* msg, size_t n);
+
+/* ---------------------------------------------------------- problems */
+
+/* Number the active nodes, build the block pattern and assemble the
+ * matrix (eqs. (1)-(4)) on the device: FP64 blocks, their complex64
+ * rounding, and the Jacobi diagonal inverse.  Section 3.1.2's assembly by
+ * degree of freedom is kept: every block row is computed by its owner from
+ * the elements around the node, with no atomics and no symbolic phase on
+ * the host. */
+int femh_problem_create(femh_ctx* ctx, const femh_problem_desc* desc, femh_problem** out);
+int femh_problem_get_info(const femh_problem* prob, femh_problem_info* info);
+void femh_problem_destroy(femh_problem* prob);
+
+/* Solve for nrhs incident waves.  H_out (host) receives
+ * [nrhs][nz+1][ny+1][nx+1][3] complex128 total-field values at the grid
+ * nodes (0 at nodes of PEC elements only); stats (host) receives nrhs
+ * entries.  Returns FEMH_OK when every right-hand side converged, else the
+ * first failing status; failed columns still hold their best iterate. */
+int femh_solve(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves,
+               const femh_solve_opts* opts, femh_c128* H_out, femh_solve_stats* stats);
+
+/* As femh_solve, with H_out a device pointer of the same layout. */
+int femh_solve_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves,
+                   const femh_solve_opts* opts, femh_c128* H_out_dev, femh_solve_stats* stats);
+
+/* Batched right-hand sides: the nrhs (<= 64) columns advance together,
+ * one complex64 block-sparse matrix times dense block (SpMM) per
+ * iteration with per-column COCG scalars, and FP64 refinement of every
+ * column to opts->rtol.  Each column follows its own single-RHS
+ * recurrence.  H_out_dev as in femh_solve_dev. */
+int femh_solve_batched_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves,
+                           const femh_solve_opts* opts, femh_c128* H_out_dev,
+                           femh_solve_stats* stats);
+
+/* ---------------------------------------------- inspection / bench hooks */
+
+/* Copy the assembled FP64 matrix to host buffers: row_ptr[n_nodes + 1],
+ * col_idx[nnzb] (ascending within a row), vals[nnzb][3][3] row-major
+ * blocks.  Any pointer may be NULL to skip it. */
+int femh_export_bsr(const femh_problem* prob, int32_t* row_ptr, int32_t* col_idx, femh_c128* vals);
+
+/* Copy the complex64 matrix values [nnzb][3][3] (interleaved floats). */
+int femh_export_bsr_c64(const femh_problem* prob, float* vals);
+
+/* Right-hand sides of eq. (4) for nrhs waves, host buffer
+ * [nrhs][n_unknowns] complex128. */
+int femh_export_rhs(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves, femh_c128* b);
+
+/* Jacobi diagonal inverse, host buffer [n_unknowns] complex128. */
+int femh_export_jacobi(const femh_problem* prob, femh_c128* dinv);
+
+/* y = A x on device vectors of n_unknowns complex entries: complex128 for
+ * FEMH_FP64, complex64 with FP32 accumulation for FEMH_MIXED.  The product
+ * runs `reps` >= 1 times; *avg_seconds (may be NULL) receives the mean
+ * kernel time measured with HIP events on the context's stream. */
+int femh_spmv_dev(femh_problem* prob, int32_t precision, const void* x_dev, void* y_dev,
+                  int32_t reps, double* avg_seconds);
+
+/* Y = A X for ncols (1..64) complex64 columns; X and Y are device arrays
+ * [n_unknowns][ncols] (column index fastest).  Timing as femh_spmv_dev. */
+int femh_spmm_dev(femh_problem* prob, int32_t ncols, const void* X_dev, void* Y_dev,
+                  int32_t reps, double* avg_seconds);
+
+/* The SpMM shape the autotuner chose for this problem (timed candidates on
+ * the first batched product): *kind = 1 matrix cores, 0 vector FMAs, -1 not
+ * tuned yet; *blocks = workgroups of the launch. */
+int femh_spmm_tile(const femh_problem* prob, int32_t* kind, int32_t* blocks);
+
+/* Override the autotuner's choice (kind 0 or 1; blocks a positive multiple
+ * of 8, at most 2048), e.g. to replay a shape tuned offline. */
+int femh_spmm_set_tile(femh_problem* prob, int32_t kind, int32_t blocks);
+
+/* Streaming copy of `bytes` bytes between two device buffers the library
+ * allocates, `reps` times; *gbps receives (read + write bytes) / mean time.
+ * The denominator for achieved-bandwidth figures. */
+int femh_bw_probe(femh_ctx* ctx, int64_t bytes, int32_t reps, double* gbps);
+
+/* Per-kernel event timing of the solvers.  When enabled, every solve
+ * records HIP events around each matrix product it launches; the totals
+ * accumulate until read.  *spmv_seconds / *spmv_launches receive the sum
+ * of kernel times and the number of products that did work, per
+ * precision (index 0 = FP64, 1 = complex64, 2 = batched SpMM). */
+int femh_profile_enable(femh_ctx* ctx, int32_t on);
+int femh_profile_read(femh_ctx* ctx, double spmv_seconds[3], int64_t spmv_launches[3],
+                      int32_t reset);
+
+/* --------------------------------------------------------------- serving */
+
+typedef struct {
+  int64_t hbm_budget_bytes;   /* admission limit on resident problem bytes; 0 = 80 % of free */
+  int32_t max_slots;          /* resident requests at once; 0 = 32 */
+  int32_t chunk_iters;        /* iterations per slot per scheduling round; 0 = 32 */
+} femh_server_opts;
+
+typedef struct {
+  int64_t submitted, completed, failed, cancelled, rejected;
+  int64_t rhs_completed;
+  double p50_seconds, p99_seconds;      /* submit -> result ready latency */
+  double requests_per_second;           /* completed / span of first submit .. last completion */
+  double rhs_per_second;
+  int64_t peak_resident_bytes;
+} femh_server_report;
+
+/* A continuous-batching request loop on its own host thread: submitted
+ * requests are admitted as memory (budget) and slots free up, assembled on
+ * the device, and advanced in rounds of chunk_iters iterations interleaved
+ * with every other resident request; finished requests retire and free
+ * their memory at once. */
+int femh_server_create(femh_ctx* ctx, const femh_server_opts* opts, femh_server** out);
+
+/* Queue a request.  All inputs are copied (host pointers only).  A request
+ * whose estimated footprint exceeds the whole budget is rejected with
+ * FEMH_E_OOM.  *ticket identifies it.  Thread-safe. */
+int femh_server_submit(femh_server* srv, const femh_problem_desc* desc, int32_t nrhs,
+                       const femh_plane_wave* waves, const femh_solve_opts* opts,
+                       uint64_t* ticket);
+
+/* Wait up to timeout_ms (0 = do not wait, < 0 = forever) for a request.
+ * On completion copies [nrhs][nz+1][ny+1][nx+1][3] into H_out (host, may be
+ * NULL) and nrhs stats, forgets the ticket and returns the request's
+ * status; FEMH_E_PENDING if still running.  Thread-safe. */
+int femh_server_poll(femh_server* srv, uint64_t ticket, int32_t timeout_ms, femh_c128* H_out,
+                     femh_solve_stats* stats);
+
+/* Cancel a request; its slot and memory are released at the next round.
+ * Other requests are unaffected.  Thread-safe. */
+int femh_server_cancel(femh_server* srv, uint64_t ticket);
+
+int femh_server_report_get(femh_server* srv, femh_server_report* out);
+
+/* Stop the loop (pending requests are cancelled) and free everything. */
+void femh_server_destroy(femh_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEMH_H */

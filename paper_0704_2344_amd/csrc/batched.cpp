@@ -1,0 +1,306 @@
+// Host driver of the batched-RHS solve: every column runs its own COCG
+// recurrence (the single-RHS algorithm, complex64 with FP32 accumulation),
+// the columns sharing one SpMM per iteration; per-column reliable updates
+// fold the complex64 partial solutions into the FP64 iterates and restart
+// each recurrence from its FP64 true residual (same search direction).
+//
+// One iteration = SpMM + per-column alpha + update + per-column beta +
+// direction update (5 kernels).  A chunk of `check_every` iterations is
+// captured once into a hipGraph and replayed; the host reads the per-column
+// state between replays (one replay queued ahead) and performs reliable
+// updates for the columns that asked for one.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "internal.h"
+
+namespace femh {
+
+namespace {
+
+constexpr size_t kPartialBytes = 2048 * 64 * 4 * sizeof(double);  // [blocks][64][4] doubles
+
+struct Scratch {
+  Ctx* ctx;
+  std::vector<void*> ptrs;
+  explicit Scratch(Ctx* c) : ctx(c) {}
+  void* get(size_t bytes) {
+    void* p = ctx->dmalloc(bytes);
+    if (p) ptrs.push_back(p);
+    return p;
+  }
+  ~Scratch() {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* p : ptrs) ctx->dfree(p);
+  }
+};
+
+// Process-wide tuning cache: (CU count, log2 of block rows) -> tile.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, BatchTile> g_tune;
+
+int ilog2(int64_t v) {
+  int l = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++l;
+  }
+  return l;
+}
+
+}  // namespace
+
+int autotune_spmm(Problem* P, const float2* Pv, float2* Qv, double* partials, const BatchScalars* sc) {
+  if (P->tile.kind >= 0) return FEMH_OK;
+  Ctx* c = P->ctx;
+  const std::pair<int, int> key(c->n_cu, ilog2(P->pat.nn));
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      P->tile = it->second;
+      P->tile.blocks = k::batched_blocks_for(P->pat.nn, c->n_cu, it->second.blocks);
+      return FEMH_OK;
+    }
+  }
+  hipStream_t s = c->stream;
+  hipEvent_t e0, e1;
+  FEMH_TRY_HIP(hipEventCreate(&e0));
+  FEMH_TRY_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  BatchTile best_tile{1, k::batched_blocks_for(P->pat.nn, c->n_cu, 4)};
+  int best_per_cu = 4;
+  const int kinds[2] = {1, 0};
+  const int per_cus[3] = {2, 4, 8};
+  for (int kind : kinds)
+    for (int pc : per_cus) {
+      BatchTile t{kind, k::batched_blocks_for(P->pat.nn, c->n_cu, pc)};
+      FEMH_TRY_HIP(k::bspmm(s, P->pat, P->val32, Pv, Qv, partials, sc, t));  // warm
+      FEMH_TRY_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) FEMH_TRY_HIP(k::bspmm(s, P->pat, P->val32, Pv, Qv, partials, sc, t));
+      FEMH_TRY_HIP(hipEventRecord(e1, s));
+      FEMH_TRY_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      FEMH_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_tile = t;
+        best_per_cu = pc;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->tile = best_tile;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = BatchTile{best_tile.kind, best_per_cu};
+  return FEMH_OK;
+}
+
+int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh_solve_opts& o,
+                  femh_solve_stats* st) {
+  Ctx* c = P->ctx;
+  hipStream_t s = c->stream;
+  const int64_t n = 3 * (int64_t)P->pat.nn;
+  const size_t v64 = 16 * (size_t)n * 64, v32 = 8 * (size_t)n * 64;
+  Scratch W(c);
+  double2* B64 = (double2*)W.get(v64);
+  double2* X64 = (double2*)W.get(v64);
+  double2* R64 = (double2*)W.get(v64);
+  float2* X32 = (float2*)W.get(v32);
+  float2* R32 = (float2*)W.get(v32);
+  float2* P32 = (float2*)W.get(v32);
+  float2* Q32 = (float2*)W.get(v32);
+  double* partials = (double*)W.get(kPartialBytes);
+  BatchScalars* sc = (BatchScalars*)W.get(sizeof(BatchScalars));
+  BatchPlan* plan = (BatchPlan*)W.get(sizeof(BatchPlan));
+  double* rr64 = (double*)W.get(64 * sizeof(double));
+  if (!B64 || !X64 || !R64 || !X32 || !R32 || !P32 || !Q32 || !partials || !sc || !plan || !rr64) {
+    set_error("device allocation failed (batched workspace)");
+    return FEMH_E_OOM;
+  }
+  const float2* dinv = P->dinv32;
+  if (o.precond == FEMH_PRECOND_NONE) {
+    float2* ones = (float2*)W.get(8 * n);
+    if (!ones) {
+      set_error("device allocation failed (identity preconditioner)");
+      return FEMH_E_OOM;
+    }
+    std::vector<float2> h((size_t)n, make_float2(1.f, 0.f));
+    FEMH_TRY_HIP(hipMemcpyAsync(ones, h.data(), 8 * n, hipMemcpyHostToDevice, s));
+    FEMH_TRY_HIP(hipStreamSynchronize(s));
+    dinv = ones;
+  }
+  const int vblocks = k::batched_vec_blocks(n);
+  const int rblocks = k::batched_blocks_for(P->pat.nn, c->n_cu, 4);
+
+  hipEvent_t t0, t1;
+  FEMH_TRY_HIP(hipEventCreate(&t0));
+  FEMH_TRY_HIP(hipEventCreate(&t1));
+  FEMH_TRY_HIP(hipEventRecord(t0, s));
+
+  FEMH_TRY_HIP(k::to_block(s, n, nrhs, b, B64));
+  FEMH_TRY_HIP(hipMemsetAsync(X64, 0, v64, s));
+  FEMH_TRY_HIP(hipMemsetAsync(X32, 0, v32, s));
+  FEMH_TRY_HIP(hipMemsetAsync(P32, 0, v32, s));
+  FEMH_TRY_HIP(k::bresidual64(s, P->pat, P->val64, X64, B64, R64, (double*)partials, rblocks, 64, rr64));
+  std::vector<double> hrr(64), bb(64), scale(64, 0.0);
+  FEMH_TRY_HIP(hipMemcpyAsync(hrr.data(), rr64, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
+
+  // host mirrors (pinned scalar block for the per-chunk reads)
+  BatchScalars* hs = reinterpret_cast<BatchScalars*>(c->pinned);
+  static_assert(sizeof(BatchScalars) <= 16384, "pinned scratch too small");
+  BatchPlan hp;
+  std::memset(hs, 0, sizeof(*hs));
+  std::memset(&hp, 0, sizeof(hp));
+  hs->max_iters = o.max_iter;
+  hs->delta2 = o.inner_rtol * o.inner_rtol;
+  hs->bd_tol = 1e-6;
+  std::vector<int> updates(64, 0), final_status(64, FEMH_OK);
+  std::vector<double> rel(64, 0.0);
+  for (int col = 0; col < 64; ++col) {
+    bb[col] = col < nrhs ? hrr[col] : 0.0;
+    if (bb[col] > 0.0) {
+      hs->done[col] = 0;
+      scale[col] = std::sqrt(bb[col]);
+      hp.action[col] = 2;
+      hp.scale[col] = 0.0;
+      hp.inv_s[col] = 1.0 / scale[col];
+      hp.ratio[col] = 1.0;
+      hp.tol2[col] = o.rtol * o.rtol;
+      rel[col] = 1.0;
+    } else {
+      hs->done[col] = 5;
+      hp.action[col] = 0;
+    }
+  }
+  FEMH_TRY_HIP(hipMemcpyAsync(sc, hs, sizeof(*hs), hipMemcpyHostToDevice, s));
+  FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
+  FEMH_TRY_HIP(k::brescale(s, n, R64, dinv, R32, P32, partials, vblocks, 64, sc, plan));
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
+  FEMH_TRY(autotune_spmm(P, P32, Q32, partials, sc));
+  const BatchTile tile = P->tile;
+
+  // one chunk of iterations, captured once
+  auto launch_chunk = [&]() -> hipError_t {
+    for (int i = 0; i < o.check_every; ++i) {
+      hipError_t e;
+      if ((e = k::bspmm(s, P->pat, P->val32, P32, Q32, partials, sc, tile)) != hipSuccess) return e;
+      if ((e = k::bred_alpha(s, partials, tile.blocks, 64, sc)) != hipSuccess) return e;
+      if ((e = k::bupdate(s, n, dinv, X32, R32, P32, Q32, partials, vblocks, sc)) != hipSuccess) return e;
+      if ((e = k::bred_beta(s, partials, vblocks, 64, sc)) != hipSuccess) return e;
+      if ((e = k::bpupdate(s, n, dinv, R32, P32, vblocks, sc, nullptr)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = true;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    hipError_t e = launch_chunk();
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess || e2 != hipSuccess || !graph ||
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+      use_graph = false;
+  } else {
+    use_graph = false;
+  }
+  (void)hipGetLastError();
+  auto run_chunk = [&]() -> hipError_t { return use_graph ? hipGraphLaunch(exec, s) : launch_chunk(); };
+
+  hipEvent_t ready;
+  FEMH_TRY_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  int status = FEMH_OK;
+  int guard = 0;
+  FEMH_TRY_HIP(run_chunk());
+  while (true) {
+    FEMH_TRY_HIP(hipMemcpyAsync(hs, sc, sizeof(*hs), hipMemcpyDeviceToHost, s));
+    FEMH_TRY_HIP(hipEventRecord(ready, s));
+    FEMH_TRY_HIP(run_chunk());
+    FEMH_TRY_HIP(hipEventSynchronize(ready));
+    bool pending = false, running = false;
+    for (int col = 0; col < 64; ++col) {
+      const int d = hs->done[col];
+      if (d >= 1 && d <= 4) pending = true;
+      if (d == 0) running = true;
+    }
+    if (!pending && !running) break;
+    if (++guard > 2 * (o.max_iter / std::max(o.check_every, 1) + 2) + 4096) {
+      status = FEMH_E_NOT_CONVERGED;
+      break;
+    }
+    if (!pending) continue;
+    // ---- reliable update of the flagged columns
+    std::memset(&hp, 0, sizeof(hp));
+    int flagged[64];
+    for (int col = 0; col < 64; ++col) {
+      const int d = hs->done[col];
+      flagged[col] = (d >= 1 && d <= 4) ? d : 0;
+      if (flagged[col]) {
+        hp.action[col] = 1;
+        hp.scale[col] = scale[col];
+      }
+    }
+    FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
+    FEMH_TRY_HIP(k::bfold(s, n, X32, X64, vblocks, plan));
+    FEMH_TRY_HIP(k::bresidual64(s, P->pat, P->val64, X64, B64, R64, (double*)partials, rblocks, 64, rr64));
+    FEMH_TRY_HIP(hipMemcpyAsync(hrr.data(), rr64, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
+    FEMH_TRY_HIP(hipStreamSynchronize(s));
+    std::memset(&hp, 0, sizeof(hp));
+    for (int col = 0; col < 64; ++col) {
+      if (!flagged[col]) continue;
+      ++updates[col];
+      rel[col] = std::sqrt(hrr[col] / bb[col]);
+      const int iters = hs->iters[col];
+      if (rel[col] <= o.rtol) {
+        hp.action[col] = 3;
+        hp.final_state[col] = 5;
+        final_status[col] = FEMH_OK;
+      } else if (flagged[col] == 2 || iters >= o.max_iter || updates[col] >= 50 * std::max(o.max_outer, 1) ||
+                 !std::isfinite(rel[col])) {
+        hp.action[col] = 3;
+        hp.final_state[col] = 6;
+        final_status[col] = FEMH_E_NOT_CONVERGED;
+      } else {
+        const double ns = std::sqrt(hrr[col]);
+        hp.action[col] = flagged[col] == 3 ? 2 : 1;
+        hp.inv_s[col] = 1.0 / ns;
+        hp.ratio[col] = scale[col] / ns;
+        hp.tol2[col] = o.rtol * o.rtol * bb[col] / (ns * ns);
+        scale[col] = ns;
+      }
+    }
+    FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
+    FEMH_TRY_HIP(k::brescale(s, n, R64, dinv, R32, P32, partials, vblocks, 64, sc, plan));
+    FEMH_TRY_HIP(k::bpupdate(s, n, dinv, R32, P32, vblocks, sc, plan->action));
+    FEMH_TRY_HIP(run_chunk());
+  }
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
+  (void)hipEventDestroy(ready);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  FEMH_TRY_HIP(k::from_block(s, n, nrhs, X64, x));
+  FEMH_TRY_HIP(hipEventRecord(t1, s));
+  FEMH_TRY_HIP(hipEventSynchronize(t1));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, t0, t1);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  for (int col = 0; col < nrhs; ++col) {
+    std::memset(&st[col], 0, sizeof(st[col]));
+    st[col].status = bb[col] > 0.0 ? final_status[col] : FEMH_OK;
+    st[col].iters = hs->iters[col];
+    st[col].outer_iters = updates[col];
+    st[col].rel_residual = bb[col] > 0.0 ? rel[col] : 0.0;
+    st[col].seconds = ms * 1e-3;
+    if (hs->done[col] < 5 && bb[col] > 0.0) st[col].status = FEMH_E_NOT_CONVERGED;
+    if (st[col].status != FEMH_OK && status == FEMH_OK) status = st[col].status;
+  }
+  if (status != FEMH_OK) set_error("batched solve: at least one column did not converge");
+  return status;
+}
+
+}  // namespace femh

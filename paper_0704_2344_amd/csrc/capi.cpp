@@ -1,0 +1,510 @@
+// extern "C" entry points of libfemh (declared in include/femh.h).
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using femh::Ctx;
+using femh::Problem;
+
+struct femh_ctx : Ctx {};
+struct femh_problem : Problem {};
+
+namespace femh {
+const char* last_error();
+}
+
+namespace {
+
+int copy_msg(const std::string& m, char* msg, size_t n) {
+  if (msg && n) {
+    std::strncpy(msg, m.c_str(), n - 1);
+    msg[n - 1] = 0;
+  }
+  return 0;
+}
+
+struct DevTmp {
+  Ctx* c;
+  void* p;
+  DevTmp(Ctx* ctx, size_t bytes) : c(ctx), p(ctx->dmalloc(bytes)) {}
+  ~DevTmp() {
+    if (p) {
+      (void)hipStreamSynchronize(c->stream);
+      c->dfree(p);
+    }
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* femh_last_error(void) { return femh::last_error(); }
+
+int femh_version(void) { return 10000; }
+
+int femh_ctx_create(int device, const femh_allocator* alloc, void* hip_stream, femh_ctx** out) {
+  femh::clear_error();
+  if (!out) {
+    femh::set_error("out is NULL");
+    return FEMH_E_INVALID;
+  }
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    femh::set_error("no HIP device available");
+    return FEMH_E_DEVICE;
+  }
+  if (device < 0 || device >= count) {
+    femh::set_error("device %d out of range (%d devices)", device, count);
+    return FEMH_E_INVALID;
+  }
+  FEMH_TRY_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  FEMH_TRY_HIP(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    femh::set_error("device %d is %s; this library is built for gfx950 only", device, prop.gcnArchName);
+    return FEMH_E_DEVICE;
+  }
+  femh_ctx* c = new femh_ctx();
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (alloc && alloc->alloc && alloc->free) c->alloc = *alloc;
+  if (hip_stream) {
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      femh::set_error("hipStreamCreate failed");
+      delete c;
+      return FEMH_E_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  if (hipHostMalloc(&c->pinned, 16384, hipHostMallocDefault) != hipSuccess) {
+    femh::set_error("hipHostMalloc failed");
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return FEMH_E_DEVICE;
+  }
+  *out = c;
+  return FEMH_OK;
+}
+
+void femh_ctx_destroy(femh_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+int femh_validate_desc(const femh_problem_desc* desc, char* msg, size_t n) {
+  femh::clear_error();
+  std::string m;
+  int st = femh::validate_desc(desc, m);
+  copy_msg(m, msg, n);
+  if (st != FEMH_OK) femh::set_error("%s", m.c_str());
+  return st;
+}
+
+int femh_validate_waves(int32_t nrhs, const femh_plane_wave* waves, char* msg, size_t n) {
+  femh::clear_error();
+  std::string m;
+  int st = femh::validate_waves(nrhs, waves, m);
+  copy_msg(m, msg, n);
+  if (st != FEMH_OK) femh::set_error("%s", m.c_str());
+  return st;
+}
+
+int femh_estimate_bytes(const femh_problem_desc* desc, int32_t nrhs, int32_t precision, int64_t* bytes) {
+  femh::clear_error();
+  std::string m;
+  int st = femh::validate_desc(desc, m);
+  if (st != FEMH_OK) {
+    femh::set_error("%s", m.c_str());
+    return st;
+  }
+  if (!bytes || nrhs < 0 || (precision != FEMH_FP64 && precision != FEMH_MIXED)) {
+    femh::set_error("bad estimate arguments");
+    return FEMH_E_INVALID;
+  }
+  *bytes = femh::estimate_bytes(desc, nrhs, precision);
+  return FEMH_OK;
+}
+
+int femh_problem_create(femh_ctx* ctx, const femh_problem_desc* desc, femh_problem** out) {
+  femh::clear_error();
+  if (!ctx || !out) {
+    femh::set_error("ctx and out must not be NULL");
+    return FEMH_E_INVALID;
+  }
+  *out = nullptr;
+  FEMH_TRY_HIP(hipSetDevice(ctx->device));
+  Problem* P = nullptr;
+  int st = femh::problem_create(ctx, desc, &P);
+  if (st != FEMH_OK) return st;
+  *out = static_cast<femh_problem*>(P);
+  return FEMH_OK;
+}
+
+int femh_problem_get_info(const femh_problem* p, femh_problem_info* info) {
+  if (!p || !info) {
+    femh::set_error("NULL argument");
+    return FEMH_E_INVALID;
+  }
+  info->grid_nodes = p->grid_nodes;
+  info->n_nodes = p->pat.nn;
+  info->n_unknowns = 3 * (int64_t)p->pat.nn;
+  info->nnzb = p->pat.nnzb;
+  info->device_bytes = p->dev_bytes;
+  return FEMH_OK;
+}
+
+void femh_problem_destroy(femh_problem* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->ctx->device);
+  delete static_cast<Problem*>(p);
+}
+
+static int upload_waves(Ctx* c, int32_t nrhs, const femh_plane_wave* waves, DevTmp& dw) {
+  if (!dw.p) {
+    femh::set_error("device allocation failed (waves)");
+    return FEMH_E_OOM;
+  }
+  FEMH_TRY_HIP(hipMemcpyAsync(dw.p, waves, sizeof(femh_plane_wave) * nrhs, hipMemcpyHostToDevice, c->stream));
+  return FEMH_OK;
+}
+
+int femh_solve_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves, const femh_solve_opts* opts,
+                   femh_c128* H_out_dev, femh_solve_stats* stats) {
+  femh::clear_error();
+  if (!prob || !H_out_dev || !stats) {
+    femh::set_error("prob, H_out and stats must not be NULL");
+    return FEMH_E_INVALID;
+  }
+  std::string m;
+  int st = femh::validate_waves(nrhs, waves, m);
+  if (st != FEMH_OK) {
+    femh::set_error("%s", m.c_str());
+    return st;
+  }
+  const femh_solve_opts o = femh::opts_with_defaults(opts);
+  if (o.precision != FEMH_FP64 && o.precision != FEMH_MIXED) {
+    femh::set_error("unknown precision %d", o.precision);
+    return FEMH_E_INVALID;
+  }
+  if (o.precond != FEMH_PRECOND_JACOBI && o.precond != FEMH_PRECOND_NONE) {
+    femh::set_error("unknown preconditioner %d", o.precond);
+    return FEMH_E_INVALID;
+  }
+  Ctx* c = prob->ctx;
+  FEMH_TRY_HIP(hipSetDevice(c->device));
+  const int64_t n = 3 * (int64_t)prob->pat.nn;
+  DevTmp dw(c, sizeof(femh_plane_wave) * nrhs);
+  FEMH_TRY(upload_waves(c, nrhs, waves, dw));
+  DevTmp db(c, 16 * n * nrhs), dx(c, 16 * n * nrhs);
+  if (!db.p || !dx.p) {
+    femh::set_error("device allocation failed (right-hand sides)");
+    return FEMH_E_OOM;
+  }
+  double2* b = (double2*)db.p;
+  double2* x = (double2*)dx.p;
+  FEMH_TRY_HIP(femh::k::rhs(c->stream, prob->mesh, prob->pat, nrhs, (const femh_plane_wave*)dw.p, b));
+  int first_bad = FEMH_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    int rc = femh::solve_single(prob, b + r * n, x + r * n, o, &stats[r]);
+    if (rc != FEMH_OK && rc != FEMH_E_NOT_CONVERGED && rc != FEMH_E_BREAKDOWN) return rc;
+    if (rc != FEMH_OK && first_bad == FEMH_OK) first_bad = rc;
+  }
+  FEMH_TRY_HIP(femh::k::scatter(c->stream, prob->mesh, prob->pat, nrhs, x, (double2*)H_out_dev));
+  FEMH_TRY_HIP(hipStreamSynchronize(c->stream));
+  return first_bad;
+}
+
+int femh_solve(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves, const femh_solve_opts* opts,
+               femh_c128* H_out, femh_solve_stats* stats) {
+  femh::clear_error();
+  if (!prob || !H_out || !stats || nrhs < 1) {
+    femh::set_error("prob, H_out and stats must not be NULL; nrhs >= 1");
+    return FEMH_E_INVALID;
+  }
+  Ctx* c = prob->ctx;
+  const size_t bytes = sizeof(femh_c128) * 3 * (size_t)prob->grid_nodes * nrhs;
+  DevTmp dh(c, bytes);
+  if (!dh.p) {
+    femh::set_error("device allocation failed (output)");
+    return FEMH_E_OOM;
+  }
+  int rc = femh_solve_dev(prob, nrhs, waves, opts, (femh_c128*)dh.p, stats);
+  if (rc != FEMH_OK && rc != FEMH_E_NOT_CONVERGED && rc != FEMH_E_BREAKDOWN) return rc;
+  FEMH_TRY_HIP(hipMemcpyAsync(H_out, dh.p, bytes, hipMemcpyDeviceToHost, c->stream));
+  FEMH_TRY_HIP(hipStreamSynchronize(c->stream));
+  return rc;
+}
+
+int femh_solve_batched_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves,
+                           const femh_solve_opts* opts, femh_c128* H_out_dev, femh_solve_stats* stats) {
+  femh::clear_error();
+  if (!prob || !H_out_dev || !stats) {
+    femh::set_error("prob, H_out and stats must not be NULL");
+    return FEMH_E_INVALID;
+  }
+  if (nrhs < 1 || nrhs > 64) {
+    femh::set_error("batched solve takes 1..64 right-hand sides (got %d)", nrhs);
+    return FEMH_E_INVALID;
+  }
+  std::string m;
+  int st = femh::validate_waves(nrhs, waves, m);
+  if (st != FEMH_OK) {
+    femh::set_error("%s", m.c_str());
+    return st;
+  }
+  const femh_solve_opts o = femh::opts_with_defaults(opts);
+  if (o.precond != FEMH_PRECOND_JACOBI && o.precond != FEMH_PRECOND_NONE) {
+    femh::set_error("unknown preconditioner %d", o.precond);
+    return FEMH_E_INVALID;
+  }
+  Ctx* c = prob->ctx;
+  FEMH_TRY_HIP(hipSetDevice(c->device));
+  const int64_t n = 3 * (int64_t)prob->pat.nn;
+  DevTmp dw(c, sizeof(femh_plane_wave) * nrhs);
+  FEMH_TRY(upload_waves(c, nrhs, waves, dw));
+  DevTmp db(c, 16 * n * nrhs), dx(c, 16 * n * nrhs);
+  if (!db.p || !dx.p) {
+    femh::set_error("device allocation failed (right-hand sides)");
+    return FEMH_E_OOM;
+  }
+  FEMH_TRY_HIP(femh::k::rhs(c->stream, prob->mesh, prob->pat, nrhs, (const femh_plane_wave*)dw.p, (double2*)db.p));
+  int rc = femh::solve_batched(prob, nrhs, (const double2*)db.p, (double2*)dx.p, o, stats);
+  if (rc != FEMH_OK && rc != FEMH_E_NOT_CONVERGED && rc != FEMH_E_BREAKDOWN) return rc;
+  FEMH_TRY_HIP(femh::k::scatter(c->stream, prob->mesh, prob->pat, nrhs, (const double2*)dx.p, (double2*)H_out_dev));
+  FEMH_TRY_HIP(hipStreamSynchronize(c->stream));
+  return rc;
+}
+
+int femh_spmm_dev(femh_problem* p, int32_t ncols, const void* X, void* Y, int32_t reps, double* avg_seconds) {
+  femh::clear_error();
+  if (!p || !X || !Y || reps < 1 || ncols < 1 || ncols > 64) {
+    femh::set_error("bad spmm arguments (1 <= ncols <= 64, reps >= 1)");
+    return FEMH_E_INVALID;
+  }
+  Ctx* c = p->ctx;
+  hipStream_t s = c->stream;
+  const int64_t n = 3 * (int64_t)p->pat.nn;
+  const bool direct = ncols == 64;
+  DevTmp xp(c, direct ? 16 : 8 * (size_t)n * 64), yp(c, direct ? 16 : 8 * (size_t)n * 64);
+  DevTmp part(c, 2048 * 64 * 4 * sizeof(double)), scd(c, sizeof(femh::BatchScalars));
+  if (!xp.p || !yp.p || !part.p || !scd.p) {
+    femh::set_error("device allocation failed (spmm)");
+    return FEMH_E_OOM;
+  }
+  const float2* Xd = (const float2*)X;
+  float2* Yd = (float2*)Y;
+  if (!direct) {
+    FEMH_TRY_HIP(hipMemsetAsync(xp.p, 0, 8 * (size_t)n * 64, s));
+    FEMH_TRY_HIP(hipMemcpy2DAsync(xp.p, 64 * 8, X, (size_t)ncols * 8, (size_t)ncols * 8, (size_t)n,
+                                  hipMemcpyDeviceToDevice, s));
+    Xd = (const float2*)xp.p;
+    Yd = (float2*)yp.p;
+  }
+  femh::BatchScalars* hs = reinterpret_cast<femh::BatchScalars*>(c->pinned);
+  std::memset(hs, 0, sizeof(*hs));
+  hs->active = 1;
+  FEMH_TRY_HIP(hipMemcpyAsync(scd.p, hs, sizeof(*hs), hipMemcpyHostToDevice, s));
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
+  FEMH_TRY(femh::autotune_spmm(p, Xd, Yd, (double*)part.p, (const femh::BatchScalars*)scd.p));
+  hipEvent_t e0, e1;
+  FEMH_TRY_HIP(hipEventCreate(&e0));
+  FEMH_TRY_HIP(hipEventCreate(&e1));
+  FEMH_TRY_HIP(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; ++i)
+    FEMH_TRY_HIP(femh::k::bspmm(s, p->pat, p->val32, Xd, Yd, (double*)part.p, (const femh::BatchScalars*)scd.p,
+                                p->tile));
+  FEMH_TRY_HIP(hipEventRecord(e1, s));
+  FEMH_TRY_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  FEMH_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+  if (avg_seconds) *avg_seconds = ms * 1e-3 / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!direct)
+    FEMH_TRY_HIP(hipMemcpy2DAsync(Y, (size_t)ncols * 8, yp.p, 64 * 8, (size_t)ncols * 8, (size_t)n,
+                                  hipMemcpyDeviceToDevice, s));
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
+  return FEMH_OK;
+}
+
+int femh_spmm_tile(const femh_problem* p, int32_t* kind, int32_t* blocks) {
+  if (!p || !kind || !blocks) {
+    femh::set_error("NULL argument");
+    return FEMH_E_INVALID;
+  }
+  *kind = p->tile.kind;
+  *blocks = p->tile.blocks;
+  return FEMH_OK;
+}
+
+int femh_spmm_set_tile(femh_problem* p, int32_t kind, int32_t blocks) {
+  if (!p || (kind != 0 && kind != 1) || blocks < 8 || blocks > 2048 || blocks % 8) {
+    femh::set_error("bad tile (kind 0/1, blocks a multiple of 8 in [8, 2048])");
+    return FEMH_E_INVALID;
+  }
+  p->tile.kind = kind;
+  p->tile.blocks = blocks;
+  return FEMH_OK;
+}
+
+// ----------------------------------------------------------------- hooks
+int femh_export_bsr(const femh_problem* p, int32_t* row_ptr, int32_t* col_idx, femh_c128* vals) {
+  femh::clear_error();
+  if (!p) {
+    femh::set_error("prob is NULL");
+    return FEMH_E_INVALID;
+  }
+  hipStream_t s = p->ctx->stream;
+  FEMH_TRY_HIP(hipSetDevice(p->ctx->device));
+  if (row_ptr) FEMH_TRY_HIP(hipMemcpyAsync(row_ptr, p->row_ptr, 4 * ((size_t)p->pat.nn + 1), hipMemcpyDeviceToHost, s));
+  if (col_idx) FEMH_TRY_HIP(hipMemcpyAsync(col_idx, p->col_idx, 4 * (size_t)p->pat.nnzb, hipMemcpyDeviceToHost, s));
+  if (vals) FEMH_TRY_HIP(hipMemcpyAsync(vals, p->val64, 144 * (size_t)p->pat.nnzb, hipMemcpyDeviceToHost, s));
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
+  return FEMH_OK;
+}
+
+int femh_export_bsr_c64(const femh_problem* p, float* vals) {
+  femh::clear_error();
+  if (!p || !vals) {
+    femh::set_error("NULL argument");
+    return FEMH_E_INVALID;
+  }
+  hipStream_t s = p->ctx->stream;
+  FEMH_TRY_HIP(hipMemcpyAsync(vals, p->val32, 72 * (size_t)p->pat.nnzb, hipMemcpyDeviceToHost, s));
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
+  return FEMH_OK;
+}
+
+int femh_export_rhs(femh_problem* p, int32_t nrhs, const femh_plane_wave* waves, femh_c128* b) {
+  femh::clear_error();
+  if (!p || !b) {
+    femh::set_error("NULL argument");
+    return FEMH_E_INVALID;
+  }
+  std::string m;
+  int st = femh::validate_waves(nrhs, waves, m);
+  if (st != FEMH_OK) {
+    femh::set_error("%s", m.c_str());
+    return st;
+  }
+  Ctx* c = p->ctx;
+  const int64_t n = 3 * (int64_t)p->pat.nn;
+  DevTmp dw(c, sizeof(femh_plane_wave) * nrhs);
+  FEMH_TRY(upload_waves(c, nrhs, waves, dw));
+  DevTmp db(c, 16 * n * nrhs);
+  if (!db.p) {
+    femh::set_error("device allocation failed");
+    return FEMH_E_OOM;
+  }
+  FEMH_TRY_HIP(femh::k::rhs(c->stream, p->mesh, p->pat, nrhs, (const femh_plane_wave*)dw.p, (double2*)db.p));
+  FEMH_TRY_HIP(hipMemcpyAsync(b, db.p, 16 * n * nrhs, hipMemcpyDeviceToHost, c->stream));
+  FEMH_TRY_HIP(hipStreamSynchronize(c->stream));
+  return FEMH_OK;
+}
+
+int femh_export_jacobi(const femh_problem* p, femh_c128* dinv) {
+  femh::clear_error();
+  if (!p || !dinv) {
+    femh::set_error("NULL argument");
+    return FEMH_E_INVALID;
+  }
+  FEMH_TRY_HIP(hipMemcpyAsync(dinv, p->dinv64, 48 * (size_t)p->pat.nn, hipMemcpyDeviceToHost, p->ctx->stream));
+  FEMH_TRY_HIP(hipStreamSynchronize(p->ctx->stream));
+  return FEMH_OK;
+}
+
+int femh_spmv_dev(femh_problem* p, int32_t precision, const void* x, void* y, int32_t reps, double* avg_seconds) {
+  femh::clear_error();
+  if (!p || !x || !y || reps < 1 || (precision != FEMH_FP64 && precision != FEMH_MIXED)) {
+    femh::set_error("bad spmv arguments");
+    return FEMH_E_INVALID;
+  }
+  Ctx* c = p->ctx;
+  hipEvent_t e0, e1;
+  FEMH_TRY_HIP(hipEventCreate(&e0));
+  FEMH_TRY_HIP(hipEventCreate(&e1));
+  FEMH_TRY_HIP(hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i) {
+    if (precision == FEMH_FP64)
+      FEMH_TRY_HIP(femh::k::spmv_c128(c->stream, p->pat, p->val64, (const double2*)x, (double2*)y, p->spmv));
+    else
+      FEMH_TRY_HIP(femh::k::spmv_c64(c->stream, p->pat, p->val32, (const float2*)x, (float2*)y, p->spmv));
+  }
+  FEMH_TRY_HIP(hipEventRecord(e1, c->stream));
+  FEMH_TRY_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  FEMH_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+  if (avg_seconds) *avg_seconds = ms * 1e-3 / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return FEMH_OK;
+}
+
+int femh_bw_probe(femh_ctx* c, int64_t bytes, int32_t reps, double* gbps) {
+  femh::clear_error();
+  if (!c || bytes < 16 || reps < 1 || !gbps) {
+    femh::set_error("bad probe arguments");
+    return FEMH_E_INVALID;
+  }
+  bytes &= ~(int64_t)15;
+  DevTmp a(c, bytes), b(c, bytes);
+  if (!a.p || !b.p) {
+    femh::set_error("device allocation failed (probe)");
+    return FEMH_E_OOM;
+  }
+  FEMH_TRY_HIP(hipMemsetAsync(a.p, 0, bytes, c->stream));
+  FEMH_TRY_HIP(femh::k::copy_probe(c->stream, (const float4*)a.p, (float4*)b.p, bytes / 16));
+  hipEvent_t e0, e1;
+  FEMH_TRY_HIP(hipEventCreate(&e0));
+  FEMH_TRY_HIP(hipEventCreate(&e1));
+  FEMH_TRY_HIP(hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i) FEMH_TRY_HIP(femh::k::copy_probe(c->stream, (const float4*)a.p, (float4*)b.p, bytes / 16));
+  FEMH_TRY_HIP(hipEventRecord(e1, c->stream));
+  FEMH_TRY_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  FEMH_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+  *gbps = 2.0 * (double)bytes / (ms * 1e-3 / reps) / 1e9;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return FEMH_OK;
+}
+
+int femh_profile_enable(femh_ctx* c, int32_t on) {
+  if (!c) {
+    femh::set_error("ctx is NULL");
+    return FEMH_E_INVALID;
+  }
+  c->profile = on != 0;
+  return FEMH_OK;
+}
+
+int femh_profile_read(femh_ctx* c, double sec[3], int64_t cnt[3], int32_t reset) {
+  if (!c || !sec || !cnt) {
+    femh::set_error("NULL argument");
+    return FEMH_E_INVALID;
+  }
+  for (int i = 0; i < 3; ++i) {
+    sec[i] = c->prof_sec[i];
+    cnt[i] = c->prof_cnt[i];
+    if (reset) {
+      c->prof_sec[i] = 0;
+      c->prof_cnt[i] = 0;
+    }
+  }
+  return FEMH_OK;
+}
+
+}  // extern "C"

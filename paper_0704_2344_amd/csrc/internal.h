@@ -1,0 +1,296 @@
+// Internal declarations of the femh library: device-side problem layout,
+// solver scalar blocks, and the launchers the host code calls.  Kernels live
+// in the .hip files; host orchestration in the .cpp files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "femh.h"
+
+namespace femh {
+
+// ----------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define FEMH_TRY_HIP(call)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      ::femh::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__,    \
+                        __LINE__);                                                           \
+      return FEMH_E_DEVICE;                                                                  \
+    }                                                                                        \
+  } while (0)
+
+#define FEMH_TRY(call)            \
+  do {                            \
+    int s_ = (call);              \
+    if (s_ != FEMH_OK) return s_; \
+  } while (0)
+
+// Faces: index f -> axis f / 2, side f % 2 (0 = minimum coordinate).
+inline int face_axis(int f) { return f >> 1; }
+inline int face_side(int f) { return f & 1; }
+
+// ------------------------------------------------- device view of a problem
+// Plain struct passed by value to kernels.
+struct MeshDev {
+  int nx, ny, nz;            // elements per axis
+  double h[3], origin[3];
+  double k0, s;
+  int abc_mask;              // bit f set = outer face f carries the ABC
+  const double2* eps;        // [ne] or null (= 1)
+  const double2* mu;         // [ne] or null (= 1)
+  const uint8_t* pec;        // [ne] or null (= none)
+};
+
+struct PatternDev {
+  int32_t nn;                // active nodes = block rows
+  int64_t nnzb;
+  const int32_t* node_id;    // [grid nodes] -> active id or -1
+  const int32_t* node_grid;  // [nn] -> grid node index
+  const uint32_t* nbr_mask;  // [nn] 27-bit neighbour mask, bit = (dz+1)*9 + (dy+1)*3 + (dx+1)
+  const int32_t* row_ptr;    // [nn + 1]
+  const int32_t* col_idx;    // [nnzb]
+};
+
+// COCG scalar block of one right-hand side, kept on the device so the
+// host never waits inside an iteration.  Complex numbers as double2.
+struct CocgScalars {
+  double2 rho;        // r^T z
+  double2 pq;         // p^T A p
+  double2 alpha, beta;
+  double rr;          // ||r||^2 (recursive)
+  double bb;          // ||b||^2 of the system being solved
+  double tol2;        // stop when rr <= tol2 * bb
+  double bd_tol;      // breakdown threshold (relative)
+  double rr_max;      // largest ||r||^2 since the last reliable update
+  double delta2;      // > 0: stop with done = 4 once rr <= delta2 * rr_max
+  int32_t iters;      // iterations done
+  int32_t max_iters;  // stop (not converged) at this count
+  int32_t done;       // 0 running, 1 converged, 2 iteration limit, 3 breakdown,
+                      // 4 residual dropped by delta: reliable update due
+  int32_t pad;
+  uint32_t ticket[4]; // last-block counters of the reduction kernels
+};
+
+// Per-column COCG scalars of a batched solve (up to 64 columns).  done[c]:
+// 0 running, 1 converged (recursive), 2 iteration limit, 3 breakdown,
+// 4 reliable update due, 5 finished, 6 finished without converging,
+// 7 finished by breakdown.
+struct BatchScalars {
+  double2 rho[64], pq[64], alpha[64], beta[64];
+  double rr[64], rr_max[64], tol2[64];
+  int32_t done[64];
+  int32_t iters[64];
+  int32_t active;     // columns with done == 0
+  int32_t max_iters;
+  uint32_t ticket;
+  int32_t pad;
+  double delta2;
+  double bd_tol;
+};
+
+// Host-written plan of one reliable update.  action[c]: 0 none, 1 fold +
+// rescale keeping the direction, 2 fold + rescale restarting the direction,
+// 3 fold and finish with final_state[c].
+struct BatchPlan {
+  int32_t action[64];
+  int32_t final_state[64];
+  double scale[64];   // fold: X64 += scale * X32
+  double inv_s[64];   // rescale: R32 = R64 * inv_s
+  double ratio[64];   // s_old / s_new
+  double tol2[64];    // recursive tolerance in the new scaling
+};
+
+// SpMM tile choice: kind 1 = matrix cores, 0 = vector FMAs; blocks = grid.
+struct BatchTile {
+  int kind;
+  int blocks;
+};
+
+// --------------------------------------------------------------- launchers
+namespace k {
+
+// ---- batched right-hand sides ([n][64] complex layout)
+int batched_blocks_for(int32_t nn, int n_cu, int per_cu);
+int batched_vec_blocks(int64_t n);
+// per-column partial sums are FP64: partials hold [blocks][64][4] doubles
+hipError_t bspmm(hipStream_t st, const PatternDev& pt, const float2* val, const float2* P, float2* Q,
+                 double* partials, const BatchScalars* sc, BatchTile tile);
+hipError_t bred_alpha(hipStream_t st, const double* partials, int nblocks, int ncols, BatchScalars* sc);
+hipError_t bupdate(hipStream_t st, int64_t n, const float2* dinv, float2* X, float2* R, const float2* P,
+                   const float2* Q, double* partials, int blocks, const BatchScalars* sc);
+hipError_t bred_beta(hipStream_t st, const double* partials, int nblocks, int ncols, BatchScalars* sc);
+hipError_t bpupdate(hipStream_t st, int64_t n, const float2* dinv, const float2* R, float2* P, int blocks,
+                    const BatchScalars* sc, const int32_t* only);
+hipError_t bresidual64(hipStream_t st, const PatternDev& pt, const double2* val, const double2* X,
+                       const double2* B, double2* R, double* partials, int blocks, int ncols, double* rr64);
+hipError_t bfold(hipStream_t st, int64_t n, float2* X32, double2* X64, int blocks, const BatchPlan* plan);
+hipError_t brescale(hipStream_t st, int64_t n, const double2* R64, const float2* dinv, float2* R32, float2* P,
+                    double* partials, int blocks, int ncols, BatchScalars* sc, const BatchPlan* plan);
+hipError_t to_block(hipStream_t st, int64_t n, int nrhs, const double2* b, double2* B);
+hipError_t from_block(hipStream_t st, int64_t n, int nrhs, const double2* X, double2* x);
+
+// Exclusive prefix sum of n int32 (n >= 0); *total (device) gets the sum.
+// tmp must hold scan_tmp_ints(n) ints.
+int64_t scan_tmp_ints(int64_t n);
+hipError_t exclusive_scan(hipStream_t st, const int32_t* in, int32_t* out, int64_t n,
+                          int32_t* tmp, int32_t* total);
+
+hipError_t check_materials(hipStream_t st, const double2* eps, const double2* mu, int64_t ne,
+                           int32_t* flag);
+hipError_t node_flags(hipStream_t st, const MeshDev& m, int32_t* flags);
+hipError_t node_compact(hipStream_t st, const MeshDev& m, const int32_t* flags,
+                        const int32_t* scan, int32_t* node_id, int32_t* node_grid);
+hipError_t row_masks(hipStream_t st, const MeshDev& m, int32_t nn, const int32_t* node_id,
+                     const int32_t* node_grid, uint32_t* mask, int32_t* counts);
+hipError_t assemble(hipStream_t st, const MeshDev& m, const PatternDev& p, int32_t* col_idx,
+                    double2* val64, float2* val32, double2* dinv64, float2* dinv32);
+hipError_t rhs(hipStream_t st, const MeshDev& m, const PatternDev& p, int32_t nrhs,
+               const femh_plane_wave* waves_dev, double2* b);
+hipError_t scatter(hipStream_t st, const MeshDev& m, const PatternDev& p, int32_t nrhs,
+                   const double2* x, double2* out);
+hipError_t copy_probe(hipStream_t st, const float4* src, float4* dst, int64_t n);
+
+// ---- Krylov kernels
+struct SpmvLaunch {
+  int blocks;       // multiple of 8 (one share per XCD)
+};
+SpmvLaunch spmv_launch_for(int32_t nn, int n_cu);
+
+hipError_t spmv_c128(hipStream_t st, const PatternDev& p, const double2* val, const double2* x,
+                     double2* y, SpmvLaunch L);
+hipError_t spmv_c64(hipStream_t st, const PatternDev& p, const float2* val, const float2* x,
+                    float2* y, SpmvLaunch L);
+
+// COCG building blocks.  Partials hold 2 * blocks doubles (or double2).
+hipError_t cocg_init_c128(hipStream_t st, int64_t n, const double2* b, const double2* dinv,
+                          double2* x, double2* r, double2* p, CocgScalars* sc, double2* partials,
+                          int zero_x);
+hipError_t cocg_spmv_dot_c128(hipStream_t st, const PatternDev& pt, const double2* val,
+                              const double2* p, double2* q, CocgScalars* sc, double2* partials,
+                              SpmvLaunch L);
+hipError_t cocg_update_c128(hipStream_t st, int64_t n, const double2* dinv, double2* x,
+                            double2* r, const double2* p, const double2* q, CocgScalars* sc,
+                            double2* partials);
+hipError_t cocg_pupdate_c128(hipStream_t st, int64_t n, const double2* dinv, const double2* r,
+                             double2* p, const CocgScalars* sc);
+
+// complex64 recurrence; its reductions accumulate in FP64 (partials hold
+// 4 doubles per workgroup)
+hipError_t cocg_spmv_dot_c64(hipStream_t st, const PatternDev& pt, const float2* val,
+                             const float2* p, float2* q, CocgScalars* sc, void* partials,
+                             SpmvLaunch L);
+hipError_t cocg_update_c64(hipStream_t st, int64_t n, const float2* dinv, float2* x, float2* r,
+                           const float2* p, const float2* q, CocgScalars* sc, void* partials);
+hipError_t cocg_pupdate_c64(hipStream_t st, int64_t n, const float2* dinv, const float2* r,
+                            float2* p, const CocgScalars* sc);
+
+// Reliable update of the complex64 recurrence: r = r64 * inv_s, z = D^-1 r;
+// rho' = r^T z.  fresh = 1: p = z (restart).  fresh = 0: beta = rho' /
+// (rho * ratio) for the direction kept in the old scaling (ratio = s_old /
+// s_new); the caller then runs cocg_pupdate_c64.  Sets tol2, clears done.
+hipError_t cocg_rescale_c64(hipStream_t st, int64_t n, const double2* r64, double inv_s,
+                            const float2* dinv, float2* r, float2* p, CocgScalars* sc,
+                            void* partials, double ratio, double tol2, int fresh);
+// x64 += s * d32 and d32 = 0
+hipError_t ir_fold(hipStream_t st, int64_t n, float2* d, double s, double2* x);
+
+// r = b - A x (FP64) and ||r||^2 -> *rr_out (device), deterministic.
+hipError_t residual_c128(hipStream_t st, const PatternDev& pt, const double2* val,
+                         const double2* x, const double2* b, double2* r, double* partials,
+                         uint32_t* ticket, double* rr_out, SpmvLaunch L);
+// ||v||^2 of a device vector into *out (device), deterministic.
+hipError_t norm2_c128(hipStream_t st, int64_t n, const double2* v, double* partials,
+                      uint32_t* ticket, double* out);
+
+int reduce_blocks_for(int64_t n);
+
+}  // namespace k
+
+// ------------------------------------------------------------- host objects
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  femh_allocator alloc{};
+  int n_cu = 256;
+  bool profile = false;
+  double prof_sec[3] = {0, 0, 0};
+  int64_t prof_cnt[3] = {0, 0, 0};
+  std::vector<hipEvent_t> ev_pool;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  void* pinned = nullptr;  // small pinned host buffer for scalar readback
+  int64_t live_bytes = 0;
+
+  void* dmalloc(size_t bytes);
+  void dfree(void* p);
+};
+
+struct Problem {
+  Ctx* ctx = nullptr;
+  MeshDev mesh{};
+  PatternDev pat{};
+  int faces[6] = {0, 0, 0, 0, 0, 0};
+  int64_t grid_nodes = 0;
+  // owned device memory
+  double2* eps = nullptr;
+  double2* mu = nullptr;
+  uint8_t* pec = nullptr;
+  int32_t* node_id = nullptr;
+  int32_t* node_grid = nullptr;
+  uint32_t* nbr_mask = nullptr;
+  int32_t* row_ptr = nullptr;
+  int32_t* col_idx = nullptr;
+  double2* val64 = nullptr;
+  float2* val32 = nullptr;
+  double2* dinv64 = nullptr;
+  float2* dinv32 = nullptr;
+  int64_t dev_bytes = 0;
+  k::SpmvLaunch spmv{};
+  BatchTile tile{-1, 0};  // autotuned SpMM shape (kind -1 = not tuned yet)
+
+  std::vector<void*> owned;
+  void* alloc(size_t bytes);  // tracked allocation, freed with the problem
+  ~Problem();
+};
+
+// Host-side helpers shared by the C API and the server.
+int validate_desc(const femh_problem_desc* d, std::string& msg);
+int validate_waves(int32_t nrhs, const femh_plane_wave* w, std::string& msg);
+int64_t estimate_bytes(const femh_problem_desc* d, int32_t nrhs, int32_t precision);
+int problem_create(Ctx* ctx, const femh_problem_desc* d, Problem** out);
+femh_solve_opts opts_with_defaults(const femh_solve_opts* o);
+
+// Solve one right-hand side already assembled into b (device, FP64) into x
+// (device, FP64).  Fills one stats entry.  Workspace is allocated inside.
+int solve_single(Problem* P, const double2* b, double2* x, const femh_solve_opts& o,
+                 femh_solve_stats* st);
+
+// Batched solve of nrhs <= 64 right-hand sides b (device, [nrhs][n] FP64)
+// into x (device, [nrhs][n] FP64): complex64 SpMM-COCG per column with
+// per-column reliable updates into FP64.
+int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh_solve_opts& o,
+                  femh_solve_stats* st);
+// Pick the SpMM tile for a problem (timed candidates), cached on the problem.
+int autotune_spmm(Problem* P, const float2* Pv, float2* Qv, double* partials, const BatchScalars* sc);
+
+// Single-RHS solve as a non-blocking state machine (one code path for
+// femh_solve and the server).  step() queues the work its phase allows and
+// acts on readbacks that have landed; wait() blocks on the oldest one.
+struct Stepper;
+Stepper* stepper_create(Problem* P, const double2* b, double2* x, const femh_solve_opts& o);
+int stepper_step(Stepper* s, bool* progress);
+bool stepper_done(const Stepper* s);
+void stepper_wait(Stepper* s);
+void stepper_stats(const Stepper* s, femh_solve_stats* st);
+void stepper_destroy(Stepper* s);
+
+}  // namespace femh

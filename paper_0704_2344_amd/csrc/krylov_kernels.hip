@@ -1,0 +1,616 @@
+// Krylov kernels: block-CSR SpMV of the 3x3-block complex matrix (complex128,
+// or complex64 with FP32 accumulation), the fused steps of conjugate
+// gradients read for a complex-symmetric matrix (COCG: unconjugated bilinear
+// form r^T z, Hermitian norm ||r|| for stopping) with diagonal
+// preconditioning (section 3.1.5.1), the FP64 true residual and the
+// iterative-refinement update.
+//
+// SpMV mapping.  One wavefront owns one block row at a time.  The row's
+// values are a contiguous run of 9 * nb complex numbers (nb <= 27 blocks on
+// a hexahedral mesh).  Lane l < 63 always handles entry e = l % 9 of blocks
+// l / 9, l / 9 + 7, l / 9 + 14, l / 9 + 21: the wave reads the run in steps
+// of 63 consecutive complex values (fully coalesced), every lane keeps a
+// fixed (row component i, column component j) so it needs one accumulator,
+// and x is gathered as x[3 col + j].  Two shuffle stages (over j, then over
+// the 7 block offsets) leave y_i in lane 3 i.  Rows are dealt to waves so
+// that the 8 XCDs (workgroups are dispatched round-robin over them) each
+// sweep a contiguous window of rows at a time, keeping the x gathers inside
+// one L2.
+//
+// Reductions are deterministic: each workgroup writes a partial, and the
+// last workgroup to finish (device-scope ticket) sums the partials in a
+// fixed order and updates the scalar block.  No floating-point atomics.
+#include "internal.h"
+
+namespace femh {
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = 64 * kWavesPerBlock;
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return make_float2(v.x, v.y);
+}
+
+template <typename R> struct Cx;
+template <> struct Cx<double> { using T = double2; };
+template <> struct Cx<float> { using T = float2; };
+
+template <typename C> __device__ __forceinline__ C mk(double re, double im);
+template <> __device__ __forceinline__ double2 mk<double2>(double re, double im) { return make_double2(re, im); }
+template <> __device__ __forceinline__ float2 mk<float2>(double re, double im) { return make_float2((float)re, (float)im); }
+
+template <typename R>
+__device__ __forceinline__ R shfl_down_z(R v, int off, int lane) {
+  R s = __shfl_down(v, off, 64);
+  return (lane + off < 64) ? s : R(0);
+}
+
+// y_i of NR block rows in lanes 0, 3, 6 (see file comment).  The rows'
+// load chains are interleaved so a wave keeps NR rows of loads in flight.
+// rows[] are wave-uniform; rows >= nn contribute nothing.
+template <typename R, int NR>
+__device__ __forceinline__ void rows_product(const PatternDev& p, const typename Cx<R>::T* __restrict__ val,
+                                             const typename Cx<R>::T* __restrict__ x, const int32_t (&rows)[NR],
+                                             int lane, R (&yr)[NR], R (&yi)[NR]) {
+  using C = typename Cx<R>::T;
+  const int e = lane % 9;
+  const int bo = lane / 9;
+  const int j = e % 3;
+  int32_t beg[NR], nb[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (rows[k] < p.nn) {
+      beg[k] = p.row_ptr[rows[k]];
+      nb[k] = p.row_ptr[rows[k] + 1] - beg[k];
+    } else {
+      beg[k] = 0;
+      nb[k] = 0;
+    }
+    if (lane >= 63) nb[k] = 0;
+  }
+  C a[NR][4];
+  int32_t c[NR][4];
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int b = bo + 7 * kk;
+      if (b < nb[k]) {
+        a[k][kk] = ld_stream(val + (size_t)(beg[k] + b) * 9 + e);
+        c[k][kk] = p.col_idx[beg[k] + b];
+      }
+    }
+  R ar[NR], ai[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    ar[k] = R(0);
+    ai[k] = R(0);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int b = bo + 7 * kk;
+      if (b < nb[k]) {
+        const C xv = x[3 * (size_t)c[k][kk] + j];
+        ar[k] += a[k][kk].x * xv.x - a[k][kk].y * xv.y;
+        ai[k] += a[k][kk].x * xv.y + a[k][kk].y * xv.x;
+      }
+    }
+  }
+  const bool keep = lane < 63 && (lane % 3) == 0;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    // stage 1: lanes with j = 0 collect j = 1, 2 of the same (block, i)
+    const R r1 = __shfl_down(ar[k], 1, 64), i1 = __shfl_down(ai[k], 1, 64);
+    const R r2 = __shfl_down(ar[k], 2, 64), i2 = __shfl_down(ai[k], 2, 64);
+    ar[k] = keep ? ar[k] + r1 + r2 : R(0);
+    ai[k] = keep ? ai[k] + i1 + i2 : R(0);
+    // stage 2: sum the 7 block offsets (lanes 9 bo + 3 i) into lanes 3 i
+    ar[k] += shfl_down_z(ar[k], 36, lane);
+    ai[k] += shfl_down_z(ai[k], 36, lane);
+    ar[k] += shfl_down_z(ar[k], 18, lane);
+    ai[k] += shfl_down_z(ai[k], 18, lane);
+    ar[k] += shfl_down_z(ar[k], 9, lane);
+    ai[k] += shfl_down_z(ai[k], 9, lane);
+    yr[k] = ar[k];
+    yi[k] = ai[k];
+  }
+}
+
+__device__ __forceinline__ int wave_row_start(int& nwaves) {
+  const int wib = threadIdx.x >> 6;
+  const int xcd = blockIdx.x & 7;
+  const int loc = blockIdx.x >> 3;
+  const int per_xcd = gridDim.x >> 3;
+  nwaves = gridDim.x * kWavesPerBlock;
+  return __builtin_amdgcn_readfirstlane((xcd * per_xcd + loc) * kWavesPerBlock + wib);
+}
+
+constexpr int kRowsPerWave = 2;  // rows a wave keeps in flight
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_spmv(PatternDev p, const typename Cx<R>::T* __restrict__ val,
+                                                 const typename Cx<R>::T* __restrict__ x,
+                                                 typename Cx<R>::T* __restrict__ y) {
+  using C = typename Cx<R>::T;
+  const int lane = threadIdx.x & 63;
+  int nwaves;
+  const int w = wave_row_start(nwaves);
+  for (int32_t r0 = w; r0 < p.nn; r0 += kRowsPerWave * nwaves) {
+    int32_t rows[kRowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) rows[k] = r0 + k * nwaves;
+    R yr[kRowsPerWave], yi[kRowsPerWave];
+    rows_product<R, kRowsPerWave>(p, val, x, rows, lane, yr, yi);
+    if (lane == 0 || lane == 3 || lane == 6) {
+#pragma unroll
+      for (int k = 0; k < kRowsPerWave; ++k)
+        if (rows[k] < p.nn) {
+          C o;
+          o.x = yr[k];
+          o.y = yi[k];
+          y[3 * (size_t)rows[k] + lane / 3] = o;
+        }
+    }
+  }
+}
+
+// ------------------------------------------------------ block reductions
+// Sum NV values of type R over the workgroup; result valid in thread 0.
+template <typename R, int NV>
+__device__ __forceinline__ void block_sum(R (&v)[NV]) {
+  __shared__ R s[kBlock / 64][NV > 0 ? NV : 1];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s[wid][i] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      R t = s[0][i];
+      for (int w = 1; w < kBlock / 64; ++w) t += s[w][i];
+      v[i] = t;
+    }
+  }
+  __syncthreads();
+}
+
+// Publish this workgroup's NV partial sums; returns true in every thread of
+// the last workgroup to arrive, whose v[] (all threads) then holds the
+// fixed-order total over all workgroups.
+template <typename R, int NV>
+__device__ __forceinline__ bool last_block_total(R (&v)[NV], R* __restrict__ partials, uint32_t* ticket) {
+  __shared__ int s_last;
+  __shared__ R s_tot[NV];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) __hip_atomic_store(&partials[(size_t)blockIdx.x * NV + i], v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const uint32_t prev = atomicAdd(ticket, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  R acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = R(0);
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      acc[i] += __hip_atomic_load(&partials[(size_t)b * NV + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  block_sum<R, NV>(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s_tot[i] = acc[i];
+    *ticket = 0u;  // ready for the next launch (kernel boundary orders it)
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = s_tot[i];
+  return true;
+}
+
+// ----------------------------------------------------------------- COCG
+// Scalar-block updates after each reduction.  All in FP64 (the complex64
+// path converts its FP32 totals).
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double s = fmax(fabs(b.x), fabs(b.y));
+  const double br = b.x / s, bi = b.y / s;
+  const double d = br * br + bi * bi;
+  return make_double2((a.x * br + a.y * bi) / (d * s), (a.y * br - a.x * bi) / (d * s));
+}
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// init: r = src (optionally x = 0), p = D^-1 r; rho = r^T p, rr = ||r||^2, zz = ||p||^2
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cocg_init(int64_t n, const double2* __restrict__ src64,
+                                                      const typename Cx<R>::T* __restrict__ dinv,
+                                                      typename Cx<R>::T* __restrict__ x,
+                                                      typename Cx<R>::T* __restrict__ r,
+                                                      typename Cx<R>::T* __restrict__ p, CocgScalars* sc,
+                                                      double* __restrict__ partials, int zero_x, const double* src_rr) {
+  using C = typename Cx<R>::T;
+  if (sc->done) return;
+  // the complex64 inner solve starts from the FP64 residual scaled to unit norm
+  const double scale = src_rr ? 1.0 / sqrt(*src_rr) : 1.0;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double2 s = src64[i];
+    C ri = mk<C>(s.x * scale, s.y * scale);
+    const C di = dinv[i];
+    C zi;
+    zi.x = di.x * ri.x - di.y * ri.y;
+    zi.y = di.x * ri.y + di.y * ri.x;
+    r[i] = ri;
+    p[i] = zi;
+    if (zero_x) x[i] = mk<C>(0.0, 0.0);
+    v[0] += (double)ri.x * zi.x - (double)ri.y * zi.y;
+    v[1] += (double)ri.x * zi.y + (double)ri.y * zi.x;
+    v[2] += (double)ri.x * ri.x + (double)ri.y * ri.y;
+    v[3] += (double)zi.x * zi.x + (double)zi.y * zi.y;
+  }
+  block_sum<double, 4>(v);
+  if (!last_block_total<double, 4>(v, partials, &sc->ticket[0])) return;
+  if (threadIdx.x == 0) {
+    const double2 rho = make_double2((double)v[0], (double)v[1]);
+    const double rr = (double)v[2], zz = (double)v[3];
+    sc->rho = rho;
+    sc->rr = rr;
+    if (src_rr || sc->bb <= 0.0) sc->bb = rr;
+    if (rr <= sc->tol2 * sc->bb) sc->done = 1;
+    else if (cabs2(rho) <= sc->bd_tol * sc->bd_tol * rr * zz) sc->done = 3;
+  }
+}
+
+// q = A p and p^T q, ||p||^2, ||q||^2; last block: alpha = rho / p^T q
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const typename Cx<R>::T* __restrict__ val,
+                                                          const typename Cx<R>::T* __restrict__ p,
+                                                          typename Cx<R>::T* __restrict__ q, CocgScalars* sc,
+                                                          double* __restrict__ partials) {
+  using C = typename Cx<R>::T;
+  if (sc->done) return;
+  const int lane = threadIdx.x & 63;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  int nwaves;
+  const int w = wave_row_start(nwaves);
+  for (int32_t r0 = w; r0 < pt.nn; r0 += kRowsPerWave * nwaves) {
+    int32_t rows[kRowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) rows[k] = r0 + k * nwaves;
+    R yr[kRowsPerWave], yi[kRowsPerWave];
+    rows_product<R, kRowsPerWave>(pt, val, p, rows, lane, yr, yi);
+    if (lane == 0 || lane == 3 || lane == 6) {
+#pragma unroll
+      for (int k = 0; k < kRowsPerWave; ++k) {
+        if (rows[k] >= pt.nn) continue;
+        const size_t idx = 3 * (size_t)rows[k] + lane / 3;
+        C o;
+        o.x = yr[k];
+        o.y = yi[k];
+        q[idx] = o;
+        const C pi = p[idx];
+        v[0] += (double)pi.x * yr[k] - (double)pi.y * yi[k];
+        v[1] += (double)pi.x * yi[k] + (double)pi.y * yr[k];
+        v[2] += (double)pi.x * pi.x + (double)pi.y * pi.y;
+        v[3] += (double)yr[k] * yr[k] + (double)yi[k] * yi[k];
+      }
+    }
+  }
+  block_sum<double, 4>(v);
+  if (!last_block_total<double, 4>(v, partials, &sc->ticket[1])) return;
+  if (threadIdx.x == 0) {
+    const double2 pq = make_double2((double)v[0], (double)v[1]);
+    sc->pq = pq;
+    if (cabs2(pq) <= sc->bd_tol * sc->bd_tol * (double)v[2] * (double)v[3]) {
+      sc->done = 3;
+    } else {
+      sc->alpha = cdiv(sc->rho, pq);
+    }
+  }
+}
+
+// x += alpha p; r -= alpha q; z = D^-1 r (not stored); rho' = r^T z, ||r||^2, ||z||^2.
+// Last block: convergence / iteration limit / breakdown, beta = rho' / rho.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t n, const typename Cx<R>::T* __restrict__ dinv,
+                                                        typename Cx<R>::T* __restrict__ x,
+                                                        typename Cx<R>::T* __restrict__ r,
+                                                        const typename Cx<R>::T* __restrict__ p,
+                                                        const typename Cx<R>::T* __restrict__ q, CocgScalars* sc,
+                                                        double* __restrict__ partials) {
+  using C = typename Cx<R>::T;
+  if (sc->done) return;
+  const R ar = (R)sc->alpha.x, ai = (R)sc->alpha.y;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const C pi = p[i], qi = q[i], di = dinv[i];
+    C xi = x[i], ri = r[i];
+    xi.x += ar * pi.x - ai * pi.y;
+    xi.y += ar * pi.y + ai * pi.x;
+    ri.x -= ar * qi.x - ai * qi.y;
+    ri.y -= ar * qi.y + ai * qi.x;
+    x[i] = xi;
+    r[i] = ri;
+    const R zr = di.x * ri.x - di.y * ri.y;
+    const R zi = di.x * ri.y + di.y * ri.x;
+    v[0] += (double)ri.x * zr - (double)ri.y * zi;
+    v[1] += (double)ri.x * zi + (double)ri.y * zr;
+    v[2] += (double)ri.x * ri.x + (double)ri.y * ri.y;
+    v[3] += (double)zr * zr + (double)zi * zi;
+  }
+  block_sum<double, 4>(v);
+  if (!last_block_total<double, 4>(v, partials, &sc->ticket[2])) return;
+  if (threadIdx.x == 0) {
+    const double2 rho_new = make_double2((double)v[0], (double)v[1]);
+    const double rr = (double)v[2], zz = (double)v[3];
+    sc->iters += 1;
+    sc->rr = rr;
+    if (rr <= sc->tol2 * sc->bb) {
+      sc->done = 1;
+    } else if (sc->iters >= sc->max_iters) {
+      sc->done = 2;
+    } else if (cabs2(rho_new) <= sc->bd_tol * sc->bd_tol * rr * zz) {
+      sc->done = 3;
+    } else {
+      bool trigger = false;
+      if (sc->delta2 > 0.0) {
+        if (rr > sc->rr_max) sc->rr_max = rr;
+        else trigger = rr <= sc->delta2 * sc->rr_max;
+      }
+      if (trigger) {
+        // keep rho = rho_{k-1}: the reliable update recomputes rho_k from the
+        // replaced residual and the direction update follows from it
+        sc->done = 4;
+      } else {
+        sc->beta = cdiv(rho_new, sc->rho);
+        sc->rho = rho_new;
+      }
+    }
+  }
+}
+
+// Reliable update (complex64 recurrence), see the launcher's comment.
+__global__ void __launch_bounds__(kBlock) k_cocg_rescale(int64_t n, const double2* __restrict__ r64, double inv_s,
+                                                         const float2* __restrict__ dinv, float2* __restrict__ r,
+                                                         float2* __restrict__ p, CocgScalars* sc,
+                                                         double* __restrict__ partials, double ratio, double tol2,
+                                                         int fresh) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double2 s = r64[i];
+    const float2 ri = make_float2((float)(s.x * inv_s), (float)(s.y * inv_s));
+    const float2 di = dinv[i];
+    const float zr = di.x * ri.x - di.y * ri.y;
+    const float zi = di.x * ri.y + di.y * ri.x;
+    r[i] = ri;
+    if (fresh) p[i] = make_float2(zr, zi);
+    v[0] += (double)ri.x * zr - (double)ri.y * zi;
+    v[1] += (double)ri.x * zi + (double)ri.y * zr;
+    v[2] += (double)ri.x * ri.x + (double)ri.y * ri.y;
+    v[3] += (double)zr * zr + (double)zi * zi;
+  }
+  block_sum<double, 4>(v);
+  if (!last_block_total<double, 4>(v, partials, &sc->ticket[3])) return;
+  if (threadIdx.x == 0) {
+    const double2 rho_new = make_double2((double)v[0], (double)v[1]);
+    const double rr = (double)v[2], zz = (double)v[3];
+    sc->tol2 = tol2;
+    sc->rr = rr;
+    sc->rr_max = rr;
+    sc->done = 0;
+    if (cabs2(rho_new) <= sc->bd_tol * sc->bd_tol * rr * zz) {
+      sc->done = 3;
+    } else if (!fresh) {
+      const double2 den = make_double2(sc->rho.x * ratio, sc->rho.y * ratio);
+      sc->beta = cdiv(rho_new, den);
+    }
+    sc->rho = rho_new;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_ir_fold(int64_t n, float2* __restrict__ d, double s,
+                                                    double2* __restrict__ x) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const float2 di = d[i];
+    double2 xi = x[i];
+    xi.x += s * (double)di.x;
+    xi.y += s * (double)di.y;
+    x[i] = xi;
+    d[i] = make_float2(0.f, 0.f);
+  }
+}
+
+// p = D^-1 r + beta p
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cocg_pupdate(int64_t n, const typename Cx<R>::T* __restrict__ dinv,
+                                                         const typename Cx<R>::T* __restrict__ r,
+                                                         typename Cx<R>::T* __restrict__ p, const CocgScalars* sc) {
+  using C = typename Cx<R>::T;
+  if (sc->done) return;
+  const R br = (R)sc->beta.x, bi = (R)sc->beta.y;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const C di = dinv[i], ri = r[i];
+    C pi = p[i];
+    const R zr = di.x * ri.x - di.y * ri.y;
+    const R zi = di.x * ri.y + di.y * ri.x;
+    const R nr = zr + br * pi.x - bi * pi.y;
+    const R ni = zi + br * pi.y + bi * pi.x;
+    pi.x = nr;
+    pi.y = ni;
+    p[i] = pi;
+  }
+}
+
+// r = b - A x (FP64) with ||r||^2
+__global__ void __launch_bounds__(kBlock) k_residual(PatternDev pt, const double2* __restrict__ val,
+                                                     const double2* __restrict__ x, const double2* __restrict__ b,
+                                                     double2* __restrict__ r, double* __restrict__ partials,
+                                                     uint32_t* ticket, double* rr_out) {
+  const int lane = threadIdx.x & 63;
+  double v[1] = {0.0};
+  int nwaves;
+  const int w = wave_row_start(nwaves);
+  for (int32_t r0 = w; r0 < pt.nn; r0 += kRowsPerWave * nwaves) {
+    int32_t rows[kRowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) rows[k] = r0 + k * nwaves;
+    double yr[kRowsPerWave], yi[kRowsPerWave];
+    rows_product<double, kRowsPerWave>(pt, val, x, rows, lane, yr, yi);
+    if (lane == 0 || lane == 3 || lane == 6) {
+#pragma unroll
+      for (int k = 0; k < kRowsPerWave; ++k) {
+        if (rows[k] >= pt.nn) continue;
+        const size_t idx = 3 * (size_t)rows[k] + lane / 3;
+        const double2 bi = b[idx];
+        const double2 ri = make_double2(bi.x - yr[k], bi.y - yi[k]);
+        r[idx] = ri;
+        v[0] += ri.x * ri.x + ri.y * ri.y;
+      }
+    }
+  }
+  block_sum<double, 1>(v);
+  if (!last_block_total<double, 1>(v, partials, ticket)) return;
+  if (threadIdx.x == 0) *rr_out = v[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_norm2(int64_t n, const double2* __restrict__ a, double* __restrict__ partials,
+                                                  uint32_t* ticket, double* out) {
+  double v[1] = {0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double2 t = a[i];
+    v[0] += t.x * t.x + t.y * t.y;
+  }
+  block_sum<double, 1>(v);
+  if (!last_block_total<double, 1>(v, partials, ticket)) return;
+  if (threadIdx.x == 0) *out = v[0];
+}
+
+}  // namespace
+
+namespace k {
+
+int reduce_blocks_for(int64_t n) {
+  int64_t b = (n + kBlock * 4 - 1) / (kBlock * 4);
+  if (b < 8) b = 8;
+  if (b > 2048) b = 2048;
+  return (int)((b + 7) / 8 * 8);
+}
+
+SpmvLaunch spmv_launch_for(int32_t nn, int n_cu) {
+  // enough waves to cover the rows once, capped at 8 workgroups per CU
+  int64_t b = ((int64_t)nn + kWavesPerBlock * kRowsPerWave - 1) / (kWavesPerBlock * kRowsPerWave);
+  int64_t cap = (int64_t)n_cu * 8;
+  if (cap > 2048) cap = 2048;  // partial-sum buffers hold 2048 workgroups
+  if (b > cap) b = cap;
+  if (b < 8) b = 8;
+  SpmvLaunch L;
+  L.blocks = (int)((b + 7) / 8 * 8);
+  return L;
+}
+
+hipError_t spmv_c128(hipStream_t st, const PatternDev& p, const double2* val, const double2* x, double2* y,
+                     SpmvLaunch L) {
+  if (p.nn == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spmv<double>, dim3(L.blocks), dim3(kBlock), 0, st, p, val, x, y);
+  return hipGetLastError();
+}
+
+hipError_t spmv_c64(hipStream_t st, const PatternDev& p, const float2* val, const float2* x, float2* y,
+                    SpmvLaunch L) {
+  if (p.nn == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spmv<float>, dim3(L.blocks), dim3(kBlock), 0, st, p, val, x, y);
+  return hipGetLastError();
+}
+
+hipError_t cocg_init_c128(hipStream_t st, int64_t n, const double2* b, const double2* dinv, double2* x, double2* r,
+                          double2* p, CocgScalars* sc, double2* partials, int zero_x) {
+  hipLaunchKernelGGL(k_cocg_init<double>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, b, dinv, x, r, p, sc,
+                     reinterpret_cast<double*>(partials), zero_x, (const double*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t cocg_spmv_dot_c128(hipStream_t st, const PatternDev& pt, const double2* val, const double2* p, double2* q,
+                              CocgScalars* sc, double2* partials, SpmvLaunch L) {
+  hipLaunchKernelGGL(k_cocg_spmv_dot<double>, dim3(L.blocks), dim3(kBlock), 0, st, pt, val, p, q, sc,
+                     reinterpret_cast<double*>(partials));
+  return hipGetLastError();
+}
+
+hipError_t cocg_update_c128(hipStream_t st, int64_t n, const double2* dinv, double2* x, double2* r, const double2* p,
+                            const double2* q, CocgScalars* sc, double2* partials) {
+  hipLaunchKernelGGL(k_cocg_update<double>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, x, r, p, q, sc,
+                     reinterpret_cast<double*>(partials));
+  return hipGetLastError();
+}
+
+hipError_t cocg_pupdate_c128(hipStream_t st, int64_t n, const double2* dinv, const double2* r, double2* p,
+                             const CocgScalars* sc) {
+  hipLaunchKernelGGL(k_cocg_pupdate<double>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, r, p, sc);
+  return hipGetLastError();
+}
+
+hipError_t cocg_spmv_dot_c64(hipStream_t st, const PatternDev& pt, const float2* val, const float2* p, float2* q,
+                             CocgScalars* sc, void* partials, SpmvLaunch L) {
+  hipLaunchKernelGGL(k_cocg_spmv_dot<float>, dim3(L.blocks), dim3(kBlock), 0, st, pt, val, p, q, sc,
+                     reinterpret_cast<double*>(partials));
+  return hipGetLastError();
+}
+
+hipError_t cocg_update_c64(hipStream_t st, int64_t n, const float2* dinv, float2* x, float2* r, const float2* p,
+                           const float2* q, CocgScalars* sc, void* partials) {
+  hipLaunchKernelGGL(k_cocg_update<float>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, x, r, p, q, sc,
+                     reinterpret_cast<double*>(partials));
+  return hipGetLastError();
+}
+
+hipError_t cocg_pupdate_c64(hipStream_t st, int64_t n, const float2* dinv, const float2* r, float2* p,
+                            const CocgScalars* sc) {
+  hipLaunchKernelGGL(k_cocg_pupdate<float>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, r, p, sc);
+  return hipGetLastError();
+}
+
+hipError_t cocg_rescale_c64(hipStream_t st, int64_t n, const double2* r64, double inv_s, const float2* dinv, float2* r,
+                            float2* p, CocgScalars* sc, void* partials, double ratio, double tol2, int fresh) {
+  hipLaunchKernelGGL(k_cocg_rescale, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, r64, inv_s, dinv, r, p, sc,
+                     reinterpret_cast<double*>(partials), ratio, tol2, fresh);
+  return hipGetLastError();
+}
+
+hipError_t ir_fold(hipStream_t st, int64_t n, float2* d, double s, double2* x) {
+  hipLaunchKernelGGL(k_ir_fold, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, d, s, x);
+  return hipGetLastError();
+}
+
+hipError_t residual_c128(hipStream_t st, const PatternDev& pt, const double2* val, const double2* x, const double2* b,
+                         double2* r, double* partials, uint32_t* ticket, double* rr_out, SpmvLaunch L) {
+  hipLaunchKernelGGL(k_residual, dim3(L.blocks), dim3(kBlock), 0, st, pt, val, x, b, r, partials, ticket, rr_out);
+  return hipGetLastError();
+}
+
+hipError_t norm2_c128(hipStream_t st, int64_t n, const double2* v, double* partials, uint32_t* ticket, double* out) {
+  hipLaunchKernelGGL(k_norm2, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, v, partials, ticket, out);
+  return hipGetLastError();
+}
+
+}  // namespace k
+}  // namespace femh

@@ -1,0 +1,401 @@
+// Host side of problem set-up: errors, contexts, descriptor validation,
+// footprint estimates and on-device numbering + assembly.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace femh {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+const char* last_error() { return g_err.c_str(); }
+
+void* Ctx::dmalloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~(size_t)255;
+  void* p = nullptr;
+  if (alloc.alloc) {
+    p = alloc.alloc(bytes, alloc.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  return p;
+}
+
+void Ctx::dfree(void* p) {
+  if (!p) return;
+  if (alloc.free) alloc.free(p, alloc.user);
+  else (void)hipFree(p);
+}
+
+void* Problem::alloc(size_t bytes) {
+  void* p = ctx->dmalloc(bytes);
+  if (p) {
+    owned.push_back(p);
+    dev_bytes += (int64_t)((bytes + 255) & ~(size_t)255);
+  }
+  return p;
+}
+
+Problem::~Problem() {
+  if (ctx) {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* p : owned) ctx->dfree(p);
+  }
+}
+
+// ---------------------------------------------------------------- checks
+static bool finite_c(const femh_c128& z) { return std::isfinite(z.re) && std::isfinite(z.im); }
+
+int validate_desc(const femh_problem_desc* d, std::string& msg) {
+  if (!d) {
+    msg = "descriptor is NULL";
+    return FEMH_E_INVALID;
+  }
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) {
+    msg = "nx, ny, nz must be >= 1";
+    return FEMH_E_INVALID;
+  }
+  const int64_t ne = (int64_t)d->nx * d->ny * d->nz;
+  const int64_t ng = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+  if (ng > (int64_t)1 << 30) {
+    msg = "mesh too large (more than 2^30 grid nodes)";
+    return FEMH_E_INVALID;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(d->h[a]) || !std::isfinite(d->origin[a])) {
+      msg = "h and origin must be finite";
+      return FEMH_E_NONFINITE;
+    }
+    if (!(d->h[a] > 0.0)) {
+      msg = "element sizes h must be > 0";
+      return FEMH_E_INVALID;
+    }
+  }
+  if (!std::isfinite(d->k0) || !std::isfinite(d->penalty_s)) {
+    msg = "k0 and penalty_s must be finite";
+    return FEMH_E_NONFINITE;
+  }
+  if (!(d->k0 > 0.0)) {
+    msg = "k0 must be > 0";
+    return FEMH_E_INVALID;
+  }
+  if (d->penalty_s < 0.0) {
+    msg = "penalty_s must be >= 0";
+    return FEMH_E_INVALID;
+  }
+  for (int f = 0; f < 6; ++f)
+    if (d->outer_face[f] != FEMH_FACE_ABC && d->outer_face[f] != FEMH_FACE_NATURAL) {
+      msg = "outer_face entries must be FEMH_FACE_ABC or FEMH_FACE_NATURAL";
+      return FEMH_E_INVALID;
+    }
+  if (d->arrays_on_device != 0 && d->arrays_on_device != 1) {
+    msg = "arrays_on_device must be 0 or 1";
+    return FEMH_E_INVALID;
+  }
+  if (!d->arrays_on_device) {
+    if (d->eps_r)
+      for (int64_t i = 0; i < ne; ++i) {
+        if (!finite_c(d->eps_r[i])) {
+          msg = "eps_r has a non-finite entry";
+          return FEMH_E_NONFINITE;
+        }
+        if (d->eps_r[i].re == 0.0 && d->eps_r[i].im == 0.0) {
+          msg = "eps_r has a zero entry";
+          return FEMH_E_INVALID;
+        }
+      }
+    if (d->mu_r)
+      for (int64_t i = 0; i < ne; ++i)
+        if (!finite_c(d->mu_r[i])) {
+          msg = "mu_r has a non-finite entry";
+          return FEMH_E_NONFINITE;
+        }
+    if (d->pec) {
+      int64_t active = 0;
+      for (int64_t i = 0; i < ne; ++i) active += d->pec[i] == 0;
+      if (active == 0) {
+        msg = "every element is PEC: no unknowns";
+        return FEMH_E_INVALID;
+      }
+    }
+  }
+  return FEMH_OK;
+}
+
+int validate_waves(int32_t nrhs, const femh_plane_wave* w, std::string& msg) {
+  if (nrhs < 1) {
+    msg = "nrhs must be >= 1";
+    return FEMH_E_INVALID;
+  }
+  if (!w) {
+    msg = "waves is NULL";
+    return FEMH_E_INVALID;
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    double dd = 0, pn = 0;
+    double pdr = 0, pdi = 0;
+    for (int c = 0; c < 3; ++c) {
+      if (!std::isfinite(w[r].d[c]) || !finite_c(w[r].p[c])) {
+        msg = "wave " + std::to_string(r) + " has a non-finite entry";
+        return FEMH_E_NONFINITE;
+      }
+      dd += w[r].d[c] * w[r].d[c];
+      pn += w[r].p[c].re * w[r].p[c].re + w[r].p[c].im * w[r].p[c].im;
+      pdr += w[r].p[c].re * w[r].d[c];
+      pdi += w[r].p[c].im * w[r].d[c];
+    }
+    if (std::fabs(dd - 1.0) > 1e-9) {
+      msg = "wave " + std::to_string(r) + ": |d| must be 1";
+      return FEMH_E_INVALID;
+    }
+    if (std::sqrt(pdr * pdr + pdi * pdi) > 1e-9 * std::fmax(1.0, std::sqrt(pn))) {
+      msg = "wave " + std::to_string(r) + ": p must be orthogonal to d";
+      return FEMH_E_INVALID;
+    }
+  }
+  return FEMH_OK;
+}
+
+// Active nodes and stored blocks of a host PEC mask (exact), or their upper
+// bounds when the mask is not on the host.
+static void count_pattern(const femh_problem_desc* d, int64_t& nn, int64_t& nnzb) {
+  const int nx = d->nx, ny = d->ny, nz = d->nz;
+  const int64_t gx = nx + 1, gy = ny + 1, gz = nz + 1;
+  const uint8_t* pec = d->arrays_on_device ? nullptr : d->pec;
+  if (!pec) {
+    nn = gx * gy * gz;
+    // with no PEC element every pair of nodes within one element shares it
+    nnzb = (3 * gx - 2) * (3 * gy - 2) * (3 * gz - 2);
+    return;
+  }
+  auto act = [&](int64_t ex, int64_t ey, int64_t ez) -> bool {
+    if (ex < 0 || ey < 0 || ez < 0 || ex >= nx || ey >= ny || ez >= nz) return false;
+    return pec[ex + nx * (ey + ny * ez)] == 0;
+  };
+  nn = 0;
+  nnzb = 0;
+  for (int64_t k = 0; k < gz; ++k)
+    for (int64_t j = 0; j < gy; ++j)
+      for (int64_t i = 0; i < gx; ++i) {
+        bool node_act = false;
+        for (int dz = -1; dz <= 0 && !node_act; ++dz)
+          for (int dy = -1; dy <= 0 && !node_act; ++dy)
+            for (int dx = -1; dx <= 0 && !node_act; ++dx) node_act = act(i + dx, j + dy, k + dz);
+        if (!node_act) continue;
+        ++nn;
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int64_t x0 = dx == 0 ? i - 1 : (dx > 0 ? i : i - 1), x1 = dx == 0 ? i : x0;
+              const int64_t y0 = dy == 0 ? j - 1 : (dy > 0 ? j : j - 1), y1 = dy == 0 ? j : y0;
+              const int64_t z0 = dz == 0 ? k - 1 : (dz > 0 ? k : k - 1), z1 = dz == 0 ? k : z0;
+              bool sh = false;
+              for (int64_t ez = z0; ez <= z1 && !sh; ++ez)
+                for (int64_t ey = y0; ey <= y1 && !sh; ++ey)
+                  for (int64_t ex = x0; ex <= x1 && !sh; ++ex) sh = act(ex, ey, ez);
+              nnzb += sh;
+            }
+      }
+}
+
+static inline int64_t al(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+int64_t estimate_bytes(const femh_problem_desc* d, int32_t nrhs, int32_t precision) {
+  int64_t nn, nnzb;
+  count_pattern(d, nn, nnzb);
+  const int64_t ne = (int64_t)d->nx * d->ny * d->nz;
+  const int64_t ng = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+  int64_t b = 0;
+  if (d->eps_r) b += al(16 * ne);
+  if (d->mu_r) b += al(16 * ne);
+  if (d->pec) b += al(ne);
+  b += al(4 * ng) + 3 * al(4 * nn) + al(4 * (nn + 1)) + al(4 * nnzb);
+  b += al(144 * nnzb) + al(72 * nnzb) + al(48 * nn) + al(24 * nn);
+  // per right-hand side: b and x (FP64), the solver's workspace (mixed: an
+  // FP64 residual and four complex64 vectors; FP64: three FP64 vectors), the
+  // scalar block and partial sums, and the output grid
+  const int64_t v64 = al(48 * nn), v32 = al(24 * nn);
+  if (nrhs > 0) {
+    const int64_t ws = precision == FEMH_MIXED ? v64 + 4 * v32 : 3 * v64;
+    b += (int64_t)nrhs * (2 * v64 + ws + (1 << 16)) + al((int64_t)nrhs * 48 * ng);
+  }
+  b += 1 << 20;  // numbering scratch, scalars
+  return b;
+}
+
+// --------------------------------------------------------- problem create
+static void fill_mesh(MeshDev& m, const femh_problem_desc* d) {
+  m.nx = d->nx;
+  m.ny = d->ny;
+  m.nz = d->nz;
+  for (int a = 0; a < 3; ++a) {
+    m.h[a] = d->h[a];
+    m.origin[a] = d->origin[a];
+  }
+  m.k0 = d->k0;
+  m.s = d->penalty_s == 0.0 ? 1.0 : d->penalty_s;
+  m.abc_mask = 0;
+  for (int f = 0; f < 6; ++f)
+    if (d->outer_face[f] == FEMH_FACE_ABC) m.abc_mask |= 1 << f;
+  m.eps = nullptr;
+  m.mu = nullptr;
+  m.pec = nullptr;
+}
+
+struct TmpBuf {
+  Ctx* ctx;
+  void* p = nullptr;
+  TmpBuf(Ctx* c, size_t bytes) : ctx(c) { p = c->dmalloc(bytes); }
+  ~TmpBuf() {
+    if (p) {
+      (void)hipStreamSynchronize(ctx->stream);
+      ctx->dfree(p);
+    }
+  }
+  template <typename T> T* as() { return reinterpret_cast<T*>(p); }
+};
+
+int problem_create(Ctx* ctx, const femh_problem_desc* d, Problem** out) {
+  std::string msg;
+  int st = validate_desc(d, msg);
+  if (st != FEMH_OK) {
+    set_error("%s", msg.c_str());
+    return st;
+  }
+  Problem* P = new Problem();
+  P->ctx = ctx;
+  fill_mesh(P->mesh, d);
+  for (int f = 0; f < 6; ++f) P->faces[f] = d->outer_face[f];
+  hipStream_t s = ctx->stream;
+  const int64_t ne = (int64_t)d->nx * d->ny * d->nz;
+  const int64_t ng = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+  P->grid_nodes = ng;
+  auto fail = [&](int code, const char* what) {
+    if (code == FEMH_E_OOM) set_error("device allocation failed: %s", what);
+    delete P;
+    return code;
+  };
+#define FEMH_ALLOC(ptr, T, count)                                   \
+  do {                                                              \
+    ptr = reinterpret_cast<T*>(P->alloc(sizeof(T) * (size_t)(count))); \
+    if (!ptr) return fail(FEMH_E_OOM, #ptr);                        \
+  } while (0)
+#define FEMH_HIP_OR_FAIL(call)                                                             \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      set_error("%s failed: %s", #call, hipGetErrorString(e_));                            \
+      delete P;                                                                            \
+      return (int)FEMH_E_DEVICE;                                                           \
+    }                                                                                      \
+  } while (0)
+
+  const hipMemcpyKind kind = d->arrays_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (d->eps_r) {
+    FEMH_ALLOC(P->eps, double2, ne);
+    FEMH_HIP_OR_FAIL(hipMemcpyAsync(P->eps, d->eps_r, 16 * ne, kind, s));
+    P->mesh.eps = P->eps;
+  }
+  if (d->mu_r) {
+    FEMH_ALLOC(P->mu, double2, ne);
+    FEMH_HIP_OR_FAIL(hipMemcpyAsync(P->mu, d->mu_r, 16 * ne, kind, s));
+    P->mesh.mu = P->mu;
+  }
+  if (d->pec) {
+    FEMH_ALLOC(P->pec, uint8_t, ne);
+    FEMH_HIP_OR_FAIL(hipMemcpyAsync(P->pec, d->pec, ne, kind, s));
+    P->mesh.pec = P->pec;
+  }
+  int32_t* hostw = reinterpret_cast<int32_t*>(ctx->pinned);
+  TmpBuf aux(ctx, 64);
+  if (!aux.p) return fail(FEMH_E_OOM, "aux");
+  int32_t* d_total = aux.as<int32_t>();
+  if (d->arrays_on_device && (d->eps_r || d->mu_r)) {
+    FEMH_HIP_OR_FAIL(hipMemsetAsync(d_total, 0, 4, s));
+    FEMH_HIP_OR_FAIL(k::check_materials(s, P->mesh.eps, P->mesh.mu, ne, d_total));
+    FEMH_HIP_OR_FAIL(hipMemcpyAsync(hostw, d_total, 4, hipMemcpyDeviceToHost, s));
+    FEMH_HIP_OR_FAIL(hipStreamSynchronize(s));
+    if (hostw[0] & 1) {
+      set_error("eps_r or mu_r has a non-finite entry");
+      delete P;
+      return FEMH_E_NONFINITE;
+    }
+    if (hostw[0] & 2) {
+      set_error("eps_r has a zero entry");
+      delete P;
+      return FEMH_E_INVALID;
+    }
+  }
+  // 1. active nodes and their compact numbering
+  const int64_t scan_n = ng > 1 ? ng : 1;
+  TmpBuf flags(ctx, 4 * scan_n), scan(ctx, 4 * scan_n), tmp(ctx, 4 * k::scan_tmp_ints(scan_n));
+  if (!flags.p || !scan.p || !tmp.p) return fail(FEMH_E_OOM, "numbering scratch");
+  FEMH_HIP_OR_FAIL(k::node_flags(s, P->mesh, flags.as<int32_t>()));
+  FEMH_HIP_OR_FAIL(k::exclusive_scan(s, flags.as<int32_t>(), scan.as<int32_t>(), ng, tmp.as<int32_t>(), d_total));
+  FEMH_HIP_OR_FAIL(hipMemcpyAsync(hostw, d_total, 4, hipMemcpyDeviceToHost, s));
+  FEMH_HIP_OR_FAIL(hipStreamSynchronize(s));
+  const int32_t nn = hostw[0];
+  if (nn <= 0) {
+    set_error("every element is PEC: no unknowns");
+    delete P;
+    return FEMH_E_INVALID;
+  }
+  FEMH_ALLOC(P->node_id, int32_t, ng);
+  FEMH_ALLOC(P->node_grid, int32_t, nn);
+  FEMH_HIP_OR_FAIL(k::node_compact(s, P->mesh, flags.as<int32_t>(), scan.as<int32_t>(), P->node_id, P->node_grid));
+  // 2. neighbour masks and row pointers (block pattern)
+  FEMH_ALLOC(P->nbr_mask, uint32_t, nn);
+  FEMH_ALLOC(P->row_ptr, int32_t, nn + 1);
+  FEMH_HIP_OR_FAIL(k::row_masks(s, P->mesh, nn, P->node_id, P->node_grid, P->nbr_mask, flags.as<int32_t>()));
+  FEMH_HIP_OR_FAIL(k::exclusive_scan(s, flags.as<int32_t>(), P->row_ptr, nn, tmp.as<int32_t>(), P->row_ptr + nn));
+  FEMH_HIP_OR_FAIL(hipMemcpyAsync(hostw, P->row_ptr + nn, 4, hipMemcpyDeviceToHost, s));
+  FEMH_HIP_OR_FAIL(hipStreamSynchronize(s));
+  const int64_t nnzb = hostw[0];
+  P->pat.nn = nn;
+  P->pat.nnzb = nnzb;
+  P->pat.node_id = P->node_id;
+  P->pat.node_grid = P->node_grid;
+  P->pat.nbr_mask = P->nbr_mask;
+  P->pat.row_ptr = P->row_ptr;
+  // 3. values: FP64 blocks, complex64 rounding, Jacobi inverse
+  FEMH_ALLOC(P->col_idx, int32_t, nnzb);
+  FEMH_ALLOC(P->val64, double2, 9 * nnzb);
+  FEMH_ALLOC(P->val32, float2, 9 * nnzb);
+  FEMH_ALLOC(P->dinv64, double2, 3 * (int64_t)nn);
+  FEMH_ALLOC(P->dinv32, float2, 3 * (int64_t)nn);
+  P->pat.col_idx = P->col_idx;
+  FEMH_HIP_OR_FAIL(k::assemble(s, P->mesh, P->pat, P->col_idx, P->val64, P->val32, P->dinv64, P->dinv32));
+  FEMH_HIP_OR_FAIL(hipStreamSynchronize(s));
+  P->spmv = k::spmv_launch_for(nn, ctx->n_cu);
+#undef FEMH_ALLOC
+#undef FEMH_HIP_OR_FAIL
+  *out = P;
+  return FEMH_OK;
+}
+
+femh_solve_opts opts_with_defaults(const femh_solve_opts* o) {
+  femh_solve_opts r{};
+  if (o) r = *o;
+  if (r.rtol <= 0.0) r.rtol = 1e-6;
+  if (r.max_iter <= 0) r.max_iter = 50000;
+  if (r.inner_rtol <= 0.0) r.inner_rtol = 1e-5;
+  if (r.max_outer <= 0) r.max_outer = 20;
+  if (r.check_every <= 0) r.check_every = 32;
+  return r;
+}
+
+}  // namespace femh

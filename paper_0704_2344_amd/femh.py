@@ -1,0 +1,512 @@
+"""ctypes binding of libfemh (include/femh.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+The raw C entry points are exposed under their C names (``femh_solve`` ...);
+``Context`` / ``Problem`` / ``Server`` wrap them for Python callers, taking
+problems and waves in the layout of the ``workloads`` package and torch
+tensors for device buffers.  PyTorch provides device memory (through an
+allocator callback bound to its caching allocator) and the stream.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+import weakref
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfemh.so")
+
+FEMH_OK = 0
+FEMH_E_INVALID = -1
+FEMH_E_NONFINITE = -2
+FEMH_E_OOM = -3
+FEMH_E_DEVICE = -4
+FEMH_E_NOT_CONVERGED = -5
+FEMH_E_BREAKDOWN = -6
+FEMH_E_CANCELLED = -7
+FEMH_E_PENDING = -8
+FEMH_E_NOT_FOUND = -9
+STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NONFINITE", -3: "OOM", -4: "DEVICE", -5: "NOT_CONVERGED",
+                -6: "BREAKDOWN", -7: "CANCELLED", -8: "PENDING", -9: "NOT_FOUND"}
+
+FEMH_FACE_ABC = 0
+FEMH_FACE_NATURAL = 1
+FEMH_FP64 = 0
+FEMH_MIXED = 1
+FEMH_PRECOND_JACOBI = 0
+FEMH_PRECOND_NONE = 1
+
+
+class FemhError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"femh status {status} ({STATUS_NAMES.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class femh_c128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class femh_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+class femh_problem_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("h", C.c_double * 3), ("origin", C.c_double * 3),
+                ("eps_r", C.c_void_p), ("mu_r", C.c_void_p), ("pec", C.c_void_p),
+                ("outer_face", C.c_int32 * 6), ("k0", C.c_double), ("penalty_s", C.c_double),
+                ("arrays_on_device", C.c_int32)]
+
+
+class femh_plane_wave(C.Structure):
+    _fields_ = [("d", C.c_double * 3), ("p", femh_c128 * 3)]
+
+
+class femh_solve_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("rtol", C.c_double),
+                ("max_iter", C.c_int32), ("inner_rtol", C.c_double), ("max_outer", C.c_int32),
+                ("check_every", C.c_int32)]
+
+
+class femh_solve_stats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("outer_iters", C.c_int32),
+                ("reserved", C.c_int32), ("rel_residual", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {"status": self.status, "iters": self.iters, "outer_iters": self.outer_iters,
+                "rel_residual": self.rel_residual, "seconds": self.seconds}
+
+
+class femh_problem_info(C.Structure):
+    _fields_ = [("grid_nodes", C.c_int64), ("n_nodes", C.c_int64), ("n_unknowns", C.c_int64),
+                ("nnzb", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+class femh_server_opts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("chunk_iters", C.c_int32)]
+
+
+class femh_server_report(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("cancelled", C.c_int64), ("rejected", C.c_int64), ("rhs_completed", C.c_int64),
+                ("p50_seconds", C.c_double), ("p99_seconds", C.c_double),
+                ("requests_per_second", C.c_double), ("rhs_per_second", C.c_double),
+                ("peak_resident_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+P = C.c_void_p
+I32 = C.c_int32
+I64 = C.c_int64
+PI64 = C.POINTER(C.c_int64)
+PD = C.POINTER(C.c_double)
+
+# name -> (restype, argtypes); the full C API of include/femh.h
+SIGNATURES = {
+    "femh_ctx_create": (C.c_int, [C.c_int, C.POINTER(femh_allocator), P, C.POINTER(P)]),
+    "femh_ctx_destroy": (None, [P]),
+    "femh_last_error": (C.c_char_p, []),
+    "femh_version": (C.c_int, []),
+    "femh_validate_desc": (C.c_int, [C.POINTER(femh_problem_desc), C.c_char_p, C.c_size_t]),
+    "femh_estimate_bytes": (C.c_int, [C.POINTER(femh_problem_desc), I32, I32, PI64]),
+    "femh_validate_waves": (C.c_int, [I32, C.POINTER(femh_plane_wave), C.c_char_p, C.c_size_t]),
+    "femh_problem_create": (C.c_int, [P, C.POINTER(femh_problem_desc), C.POINTER(P)]),
+    "femh_problem_get_info": (C.c_int, [P, C.POINTER(femh_problem_info)]),
+    "femh_problem_destroy": (None, [P]),
+    "femh_solve": (C.c_int, [P, I32, C.POINTER(femh_plane_wave), C.POINTER(femh_solve_opts), P,
+                             C.POINTER(femh_solve_stats)]),
+    "femh_solve_dev": (C.c_int, [P, I32, C.POINTER(femh_plane_wave), C.POINTER(femh_solve_opts), P,
+                                 C.POINTER(femh_solve_stats)]),
+    "femh_solve_batched_dev": (C.c_int, [P, I32, C.POINTER(femh_plane_wave), C.POINTER(femh_solve_opts), P,
+                                         C.POINTER(femh_solve_stats)]),
+    "femh_export_bsr": (C.c_int, [P, P, P, P]),
+    "femh_export_bsr_c64": (C.c_int, [P, P]),
+    "femh_export_rhs": (C.c_int, [P, I32, C.POINTER(femh_plane_wave), P]),
+    "femh_export_jacobi": (C.c_int, [P, P]),
+    "femh_spmv_dev": (C.c_int, [P, I32, P, P, I32, PD]),
+    "femh_spmm_dev": (C.c_int, [P, I32, P, P, I32, PD]),
+    "femh_spmm_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
+    "femh_spmm_set_tile": (C.c_int, [P, I32, I32]),
+    "femh_bw_probe": (C.c_int, [P, I64, I32, PD]),
+    "femh_profile_enable": (C.c_int, [P, I32]),
+    "femh_profile_read": (C.c_int, [P, C.c_double * 3, C.c_int64 * 3, I32]),
+    "femh_server_create": (C.c_int, [P, C.POINTER(femh_server_opts), C.POINTER(P)]),
+    "femh_server_submit": (C.c_int, [P, C.POINTER(femh_problem_desc), I32, C.POINTER(femh_plane_wave),
+                                     C.POINTER(femh_solve_opts), C.POINTER(C.c_uint64)]),
+    "femh_server_poll": (C.c_int, [P, C.c_uint64, I32, P, C.POINTER(femh_solve_stats)]),
+    "femh_server_cancel": (C.c_int, [P, C.c_uint64]),
+    "femh_server_report_get": (C.c_int, [P, C.POINTER(femh_server_report)]),
+    "femh_server_destroy": (None, [P]),
+}
+
+_lib = None
+
+# Live handles, closed children-first at interpreter exit (before torch, whose
+# allocator serves the library's device memory, is torn down).
+_live_children = weakref.WeakSet()
+_live_contexts = weakref.WeakSet()
+
+
+def _close_all():
+    for obj in list(_live_children):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    for obj in list(_live_contexts):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+_atexit_registered = False
+
+
+def _register_exit_cleanup():
+    # registered after torch is imported, so it runs before torch's own
+    # exit handlers (atexit runs in reverse order of registration)
+    global _atexit_registered
+    if not _atexit_registered:
+        atexit.register(_close_all)
+        _atexit_registered = True
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libfemh.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libfemh.so not found at {path}: build it with "
+                          f"`python -m paper_0704_2344_amd.build` (there is no CPU fallback)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def __getattr__(name):
+    # femh.femh_solve etc. resolve to the C entry points
+    if name.startswith("femh_") and name in SIGNATURES:
+        return getattr(load(), name)
+    raise AttributeError(name)
+
+
+def last_error() -> str:
+    return load().femh_last_error().decode()
+
+
+def check(status: int, ok=(FEMH_OK,)):
+    if status not in ok:
+        raise FemhError(status, last_error())
+    return status
+
+
+# --------------------------------------------------------------- marshalling
+def _c128_array(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+class _Keep:
+    """Holds host arrays alive while a descriptor that points at them is used."""
+
+    def __init__(self):
+        self.items = []
+
+    def add(self, x):
+        self.items.append(x)
+        return x
+
+
+def make_desc(prob, device_arrays: Optional[dict] = None, keep: Optional[_Keep] = None) -> femh_problem_desc:
+    """femh_problem_desc from a workloads.Problem.  With device_arrays
+    ({"eps_r": tensor, "mu_r": tensor, "pec": tensor}) the descriptor points
+    at device memory instead of the problem's host arrays."""
+    d = femh_problem_desc()
+    d.nx, d.ny, d.nz = prob.nx, prob.ny, prob.nz
+    for a in range(3):
+        d.h[a] = prob.h[a]
+        d.origin[a] = prob.origin[a]
+    for f in range(6):
+        d.outer_face[f] = int(prob.faces[f])
+    d.k0 = prob.k0
+    d.penalty_s = prob.penalty_s
+    if device_arrays is not None:
+        d.arrays_on_device = 1
+        d.eps_r = device_arrays["eps_r"].data_ptr() if device_arrays.get("eps_r") is not None else None
+        d.mu_r = device_arrays["mu_r"].data_ptr() if device_arrays.get("mu_r") is not None else None
+        d.pec = device_arrays["pec"].data_ptr() if device_arrays.get("pec") is not None else None
+        return d
+    keep = keep if keep is not None else _Keep()
+    eps = keep.add(_c128_array(prob.eps_r).reshape(-1))
+    mu = keep.add(_c128_array(prob.mu_r).reshape(-1))
+    pec = keep.add(np.ascontiguousarray(np.asarray(prob.pec, dtype=np.uint8).reshape(-1)))
+    d.eps_r = eps.ctypes.data
+    d.mu_r = mu.ctypes.data
+    d.pec = pec.ctypes.data
+    d._keep = keep  # noqa: SLF001  (keeps the arrays alive with the struct)
+    return d
+
+
+def make_waves(waves: Sequence) -> "C.Array":
+    arr = (femh_plane_wave * len(waves))()
+    for i, w in enumerate(waves):
+        dvec = np.asarray(w.d, dtype=np.float64)
+        pvec = np.asarray(w.p, dtype=np.complex128)
+        for c in range(3):
+            arr[i].d[c] = float(dvec[c])
+            arr[i].p[c].re = float(pvec[c].real)
+            arr[i].p[c].im = float(pvec[c].imag)
+    return arr
+
+
+def make_opts(precision=FEMH_FP64, rtol=1e-6, max_iter=0, inner_rtol=0.0, max_outer=0,
+              check_every=0, precond=FEMH_PRECOND_JACOBI) -> femh_solve_opts:
+    o = femh_solve_opts()
+    o.precision = precision
+    o.precond = precond
+    o.rtol = rtol
+    o.max_iter = max_iter
+    o.inner_rtol = inner_rtol
+    o.max_outer = max_outer
+    o.check_every = check_every
+    return o
+
+
+# ----------------------------------------------------------- torch bridge
+class TorchAllocator:
+    """femh_allocator backed by torch's caching allocator on one device and
+    stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+
+        self.torch = torch
+        self.device = device
+        self.stream = torch.cuda.current_stream(device)
+        self._alloc = ALLOC_FN(self._do_alloc)
+        self._free = FREE_FN(self._do_free)
+        self.struct = femh_allocator(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, user):
+        try:
+            return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        except Exception:  # out of memory -> NULL; the library reports FEMH_E_OOM
+            return None
+
+    def _do_free(self, ptr, user):
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+
+class Context:
+    """A femh context on a torch device, launching on torch's current stream."""
+
+    def __init__(self, device: int = 0, use_torch: bool = True):
+        self.lib = load()
+        self.device = device
+        h = C.c_void_p()
+        self.handle = None
+        if use_torch:
+            import torch
+
+            torch.cuda.set_device(device)
+            self.allocator = TorchAllocator(device)
+            stream = C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+            check(self.lib.femh_ctx_create(device, C.byref(self.allocator.struct), stream, C.byref(h)))
+        else:
+            self.allocator = None
+            check(self.lib.femh_ctx_create(device, None, None, C.byref(h)))
+        self.handle = h
+        self.children = weakref.WeakSet()
+        _live_contexts.add(self)
+        _register_exit_cleanup()
+
+    def close(self):
+        if self.handle:
+            for ch in list(self.children):
+                ch.close()
+            self.lib.femh_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bw_probe(self, nbytes: int = 1 << 30, reps: int = 10) -> float:
+        g = C.c_double()
+        check(self.lib.femh_bw_probe(self.handle, nbytes, reps, C.byref(g)))
+        return g.value
+
+    def profile(self, on: bool):
+        check(self.lib.femh_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self, reset=True):
+        sec = (C.c_double * 3)()
+        cnt = (C.c_int64 * 3)()
+        check(self.lib.femh_profile_read(self.handle, sec, cnt, 1 if reset else 0))
+        return list(sec), list(cnt)
+
+
+class Problem:
+    """An assembled problem resident on the device."""
+
+    def __init__(self, ctx: Context, prob, device_arrays: Optional[dict] = None):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.spec = prob
+        keep = _Keep()
+        desc = make_desc(prob, device_arrays, keep)
+        h = C.c_void_p()
+        check(self.lib.femh_problem_create(ctx.handle, C.byref(desc), C.byref(h)))
+        self.handle = h
+        ctx.children.add(self)
+        _live_children.add(self)
+        info = femh_problem_info()
+        check(self.lib.femh_problem_get_info(h, C.byref(info)))
+        self.info = info
+        self.n_nodes = info.n_nodes
+        self.n_unknowns = info.n_unknowns
+        self.nnzb = info.nnzb
+        self.grid_nodes = info.grid_nodes
+
+    def close(self):
+        if self.handle:
+            self.lib.femh_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def grid_shape(self, nrhs):
+        s = self.spec
+        return (nrhs, s.nz + 1, s.ny + 1, s.nx + 1, 3)
+
+    def solve(self, waves, **opt_kw):
+        """Host-output solve: returns (H[nrhs, nz+1, ny+1, nx+1, 3], stats list, status)."""
+        w = make_waves(waves)
+        o = make_opts(**opt_kw)
+        out = np.zeros(self.grid_shape(len(waves)), dtype=np.complex128)
+        stats = (femh_solve_stats * len(waves))()
+        st = self.lib.femh_solve(self.handle, len(waves), w, C.byref(o), out.ctypes.data, stats)
+        check(st, ok=(FEMH_OK, FEMH_E_NOT_CONVERGED, FEMH_E_BREAKDOWN))
+        return out, [s.as_dict() for s in stats], st
+
+    def solve_dev(self, waves, out_tensor, batched: bool = False, **opt_kw):
+        """Device-output solve into a complex128 torch tensor of grid shape."""
+        w = make_waves(waves)
+        o = make_opts(**opt_kw)
+        stats = (femh_solve_stats * len(waves))()
+        fn = self.lib.femh_solve_batched_dev if batched else self.lib.femh_solve_dev
+        st = fn(self.handle, len(waves), w, C.byref(o), out_tensor.data_ptr(), stats)
+        check(st, ok=(FEMH_OK, FEMH_E_NOT_CONVERGED, FEMH_E_BREAKDOWN))
+        return [s.as_dict() for s in stats], st
+
+    def export_bsr(self):
+        row_ptr = np.zeros(self.n_nodes + 1, dtype=np.int32)
+        col = np.zeros(self.nnzb, dtype=np.int32)
+        vals = np.zeros((self.nnzb, 3, 3), dtype=np.complex128)
+        check(self.lib.femh_export_bsr(self.handle, row_ptr.ctypes.data, col.ctypes.data, vals.ctypes.data))
+        return row_ptr, col, vals
+
+    def export_bsr_c64(self):
+        vals = np.zeros((self.nnzb, 3, 3), dtype=np.complex64)
+        check(self.lib.femh_export_bsr_c64(self.handle, vals.ctypes.data))
+        return vals
+
+    def export_rhs(self, waves):
+        w = make_waves(waves)
+        b = np.zeros((len(waves), self.n_unknowns), dtype=np.complex128)
+        check(self.lib.femh_export_rhs(self.handle, len(waves), w, b.ctypes.data))
+        return b
+
+    def export_jacobi(self):
+        d = np.zeros(self.n_unknowns, dtype=np.complex128)
+        check(self.lib.femh_export_jacobi(self.handle, d.ctypes.data))
+        return d
+
+    def spmv_dev(self, x, y, precision=FEMH_FP64, reps=1):
+        t = C.c_double()
+        check(self.lib.femh_spmv_dev(self.handle, precision, x.data_ptr(), y.data_ptr(), reps, C.byref(t)))
+        return t.value
+
+    def spmm_tile(self):
+        kind, blocks = I32(), I32()
+        check(self.lib.femh_spmm_tile(self.handle, C.byref(kind), C.byref(blocks)))
+        return kind.value, blocks.value
+
+    def spmm_set_tile(self, kind, blocks):
+        check(self.lib.femh_spmm_set_tile(self.handle, kind, blocks))
+
+    def spmm_dev(self, X, Y, reps=1):
+        t = C.c_double()
+        check(self.lib.femh_spmm_dev(self.handle, X.shape[1], X.data_ptr(), Y.data_ptr(), reps, C.byref(t)))
+        return t.value
+
+
+class Server:
+    """Continuous-batching request loop (femh_server_*)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes=0, max_slots=0, chunk_iters=0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        o = femh_server_opts(hbm_budget_bytes, max_slots, chunk_iters)
+        h = C.c_void_p()
+        check(self.lib.femh_server_create(ctx.handle, C.byref(o), C.byref(h)))
+        self.handle = h
+        ctx.children.add(self)
+        _live_children.add(self)
+
+    def submit(self, prob, waves, **opt_kw) -> int:
+        keep = _Keep()
+        desc = make_desc(prob, None, keep)
+        w = make_waves(waves)
+        o = make_opts(**opt_kw)
+        t = C.c_uint64()
+        check(self.lib.femh_server_submit(self.handle, C.byref(desc), len(waves), w, C.byref(o), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket, nrhs, grid_shape=None, timeout_ms=-1, want_field=True):
+        out = np.zeros(grid_shape, dtype=np.complex128) if (want_field and grid_shape) else None
+        stats = (femh_solve_stats * nrhs)()
+        st = self.lib.femh_server_poll(self.handle, ticket, timeout_ms,
+                                       out.ctypes.data if out is not None else None, stats)
+        return st, out, [s.as_dict() for s in stats]
+
+    def cancel(self, ticket):
+        return self.lib.femh_server_cancel(self.handle, ticket)
+
+    def report(self):
+        r = femh_server_report()
+        check(self.lib.femh_server_report_get(self.handle, C.byref(r)))
+        return r.as_dict()
+
+    def close(self):
+        if self.handle:
+            self.lib.femh_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

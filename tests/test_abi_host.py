@@ -1,0 +1,173 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load and export every function include/femh.h declares;
+descriptor and wave validation, and the device-footprint estimate, run on
+the host and are checked against the exact counts of the mesh bookkeeping.
+"""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_0704_2344_amd import femh as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "femh.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*)\s+(femh_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(F.LIB_PATH):
+        pytest.fail("libfemh.so is not built: run `python -m paper_0704_2344_amd.build`")
+    return F.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in femh.h but not exported"
+    # and the binding knows the signature of every one of them
+    assert set(names) == set(F.SIGNATURES)
+
+
+def test_library_targets_gfx950_only():
+    data = open(F.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+    for other in (b"gfx942", b"gfx90a", b"gfx1100", b"gfx906"):
+        assert other not in data
+
+
+def _desc(prob):
+    keep = F._Keep()
+    return F.make_desc(prob, None, keep), keep
+
+
+def _validate(lib, prob):
+    d, keep = _desc(prob)
+    buf = C.create_string_buffer(256)
+    st = lib.femh_validate_desc(C.byref(d), buf, 256)
+    return st, buf.value.decode()
+
+
+def test_validation_accepts_workloads(lib):
+    for name, make in W.WORKLOADS.items():
+        if name == "pec_sphere_shell_60":
+            continue  # big host scan; covered by the estimate test
+        p, waves = make()
+        st, msg = _validate(lib, p)
+        assert st == F.FEMH_OK, msg
+        w = F.make_waves(waves)
+        buf = C.create_string_buffer(256)
+        assert lib.femh_validate_waves(len(waves), w, buf, 256) == F.FEMH_OK
+
+
+def test_validation_rejects_bad_descriptors(lib):
+    p, _ = W.free_cube(3)
+    bad = []
+    q = W._blank(0, 3, 3, (0.1,) * 3, (0, 0, 0), 1.0)
+    bad.append((q, F.FEMH_E_INVALID))
+    q, _ = W.free_cube(3)
+    q.h = (0.1, -0.1, 0.1)
+    bad.append((q, F.FEMH_E_INVALID))
+    q, _ = W.free_cube(3)
+    q.k0 = 0.0
+    bad.append((q, F.FEMH_E_INVALID))
+    q, _ = W.free_cube(3)
+    q.k0 = float("nan")
+    bad.append((q, F.FEMH_E_NONFINITE))
+    q, _ = W.free_cube(3)
+    q.eps_r[1, 1, 1] = np.nan
+    bad.append((q, F.FEMH_E_NONFINITE))
+    q, _ = W.free_cube(3)
+    q.eps_r[0, 0, 0] = 0.0
+    bad.append((q, F.FEMH_E_INVALID))
+    q, _ = W.free_cube(3)
+    q.pec[:] = 1
+    bad.append((q, F.FEMH_E_INVALID))
+    q, _ = W.free_cube(3)
+    q.faces = (0, 0, 7, 0, 0, 0)
+    bad.append((q, F.FEMH_E_INVALID))
+    q, _ = W.free_cube(3)
+    q.penalty_s = -1.0
+    bad.append((q, F.FEMH_E_INVALID))
+    for prob, want in bad:
+        st, msg = _validate(lib, prob)
+        assert st == want, (st, msg)
+        assert msg
+        assert F.last_error()
+
+
+def test_wave_validation(lib):
+    buf = C.create_string_buffer(256)
+    good = W.PlaneWave(d=np.array([0.0, 0.0, 1.0]), p=np.array([1.0, 0.0, 0.0], np.complex128))
+    assert lib.femh_validate_waves(1, F.make_waves([good]), buf, 256) == F.FEMH_OK
+    not_unit = W.PlaneWave(d=np.array([0.0, 0.0, 2.0]), p=np.array([1.0, 0.0, 0.0], np.complex128))
+    assert lib.femh_validate_waves(1, F.make_waves([not_unit]), buf, 256) == F.FEMH_E_INVALID
+    not_perp = W.PlaneWave(d=np.array([0.0, 0.0, 1.0]), p=np.array([0.0, 0.3j, 1.0], np.complex128))
+    assert lib.femh_validate_waves(1, F.make_waves([not_perp]), buf, 256) == F.FEMH_E_INVALID
+    nan = W.PlaneWave(d=np.array([0.0, 0.0, 1.0]), p=np.array([np.nan, 0.0, 0.0], np.complex128))
+    assert lib.femh_validate_waves(1, F.make_waves([nan]), buf, 256) == F.FEMH_E_NONFINITE
+    assert lib.femh_validate_waves(0, F.make_waves([good]), buf, 256) == F.FEMH_E_INVALID
+
+
+def _estimate(lib, prob, nrhs=1, prec=F.FEMH_FP64):
+    d, keep = _desc(prob)
+    out = C.c_int64()
+    assert lib.femh_estimate_bytes(C.byref(d), nrhs, prec, C.byref(out)) == F.FEMH_OK
+    return out.value
+
+
+@pytest.mark.parametrize("name,nn,nnzb", [
+    # active nodes and 3x3 blocks of the workloads (exact bookkeeping)
+    ("free_cube_10", 1331, 29791),
+    ("pec_cube_30", 29062, 729182),
+])
+def test_footprint_estimate_counts(lib, name, nn, nnzb):
+    from oracle import fem
+    p, _ = W.WORKLOADS[name]()
+    mesh = fem.Mesh(p)
+    assert mesh.n_nodes == nn
+    est = _estimate(lib, p, nrhs=0)
+    # matrix values dominate: 144 + 72 bytes per block (+ 4 for the column index)
+    assert est >= 216 * nnzb
+    ne = p.nx * p.ny * p.nz
+    assert est <= 220 * nnzb + 100 * nn + 4 * mesh.node_active.size + 33 * ne + (2 << 20)
+    # blocks = node pairs sharing an active element (oracle pattern)
+    rp, ci = fem.block_pattern(p)
+    assert len(ci) == nnzb
+
+
+def test_footprint_estimate_grows_with_rhs_and_precision(lib):
+    p, _ = W.free_cube(10)
+    e1 = _estimate(lib, p, 1, F.FEMH_FP64)
+    e4 = _estimate(lib, p, 4, F.FEMH_FP64)
+    em = _estimate(lib, p, 1, F.FEMH_MIXED)
+    assert e4 > e1 and em > e1 - 5 * 48 * 1331
+
+
+def test_context_without_gpu_reports_device_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    st = lib.femh_ctx_create(0, None, None, C.byref(h))
+    assert st == F.FEMH_E_DEVICE
+    assert "device" in F.last_error().lower()
+    assert not h.value
+
+
+def test_null_handles_are_safe(lib):
+    lib.femh_ctx_destroy(None)
+    lib.femh_problem_destroy(None)
+    lib.femh_server_destroy(None)
+    assert lib.femh_problem_get_info(None, None) == F.FEMH_E_INVALID

@@ -1,0 +1,307 @@
+"""GPU parity: the HIP library against the CPU FP64 oracle.
+
+Everything is called through the C ABI.  Small cases compare every output
+element; the full-size workloads compare the whole assembled matrix (or
+sampled rows computed one by one by the oracle) and the solve's backward
+error under the oracle's own matrix, a property that holds at any size.
+
+Tolerances:
+  assembly / RHS / Jacobi (FP64)      max |gpu - oracle| <= 1e-13 max |oracle|
+  complex64 values                     bit-exact rounding of the FP64 values
+  SpMV complex128                      <= 1e-13 (|A| |x|) per entry
+  SpMV complex64, FP32 accumulation    <= 2e-6 (|A32| |x32|) per entry
+  FP64 solve                           relative L2 error <= 1e-9 vs LU
+  mixed solve                          relative L2 error <= 1e-6 vs LU
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import fem, solve
+from paper_0704_2344_amd import femh as F
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def small_cases():
+    rng = np.random.default_rng(11)
+    cases = {}
+    cases["free_cube_10"] = W.free_cube(10)
+    p = W.random_small(rng, n=(5, 4, 6), n_pec=6, lossy=True)
+    p.mu_r[:] = rng.uniform(1.0, 1.5, size=p.mu_r.shape) - 0.05j
+    cases["random_pec_lossy"] = (p, [W.random_wave(rng) for _ in range(2)])
+    p = W.random_small(rng, n=(7, 3, 4), n_pec=3, h=(0.05, 0.11, 0.08))
+    p.origin = (-0.3, 0.25, 1.0)
+    p.faces = (W.FACE_ABC, W.FACE_NATURAL, W.FACE_ABC, W.FACE_ABC, W.FACE_NATURAL, W.FACE_ABC)
+    p.penalty_s = 0.5
+    cases["aniso_partial_abc"] = (p, [W.random_wave(rng)])
+    p = W.random_small(rng, n=(1, 1, 1), n_pec=0)
+    cases["one_element"] = (p, [W.random_wave(rng)])
+    p = W.random_small(rng, n=(9, 1, 2), n_pec=2)
+    cases["thin_slab"] = (p, [W.random_wave(rng)])
+    p, waves = W.pec_sphere_shell(n=14, radius=0.3, shell=0.12, seed=3)
+    cases["sphere_shell_14"] = (p, waves)
+    return cases
+
+
+CASES = small_cases()
+
+
+def gpu_csr(P):
+    rp, ci, vals = P.export_bsr()
+    n = P.n_unknowns
+    A = sp.bsr_matrix((vals, ci, rp), shape=(n, n)).tocsr()
+    return rp, ci, vals, A
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_assembly_matches_oracle(ctx, name):
+    prob, waves = CASES[name]
+    P = F.Problem(ctx, prob)
+    rp, ci, vals, Ag = gpu_csr(P)
+    orp, oci = fem.block_pattern(prob)
+    assert P.n_nodes == len(orp) - 1
+    np.testing.assert_array_equal(rp, orp)        # block pattern: exact
+    np.testing.assert_array_equal(ci, oci)
+    Ao = fem.assemble(prob)
+    scale = abs(Ao).max()
+    assert abs(Ag - Ao).max() <= 1e-13 * scale
+    # complex64 copy is the rounding of the FP64 values, bit for bit
+    v32 = P.export_bsr_c64()
+    np.testing.assert_array_equal(v32, vals.astype(np.complex64))
+    # Jacobi inverse of the diagonal
+    dinv = P.export_jacobi()
+    np.testing.assert_allclose(dinv, 1.0 / Ao.diagonal(), rtol=1e-13, atol=0)
+    # right-hand sides of eq. (4)
+    bg = P.export_rhs(waves)
+    bo = fem.rhs(prob, waves).T
+    assert abs(bg - bo).max() <= 1e-13 * max(abs(bo).max(), 1e-300)
+    P.close()
+
+
+def _randvec(rng, n):
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("name", ["free_cube_10", "random_pec_lossy", "sphere_shell_14", "one_element"])
+def test_spmv_matches_oracle(ctx, torch, name):
+    prob, _ = CASES[name]
+    P = F.Problem(ctx, prob)
+    Ao = fem.assemble(prob)
+    rng = np.random.default_rng(5)
+    x = _randvec(rng, P.n_unknowns)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.zeros_like(xt)
+    P.spmv_dev(xt, yt, precision=F.FEMH_FP64, reps=2)
+    y = yt.cpu().numpy()
+    bound = abs(Ao) @ abs(x)
+    assert np.all(abs(y - Ao @ x) <= 1e-13 * bound + 1e-300)
+    # complex64 values and vector, FP32 accumulation
+    v32 = P.export_bsr_c64()
+    rp, ci, _ = P.export_bsr()
+    A32 = sp.bsr_matrix((v32.astype(np.complex128), ci, rp), shape=Ao.shape).tocsr()
+    x32 = x.astype(np.complex64)
+    xt32 = torch.from_numpy(x32).cuda()
+    yt32 = torch.zeros_like(xt32)
+    P.spmv_dev(xt32, yt32, precision=F.FEMH_MIXED, reps=2)
+    y32 = yt32.cpu().numpy().astype(np.complex128)
+    ref = A32 @ x32.astype(np.complex128)
+    bound32 = abs(A32) @ abs(x32.astype(np.complex128))
+    assert np.all(abs(y32 - ref) <= 2e-6 * bound32 + 1e-30)
+    P.close()
+
+
+def _lu_solution(prob, waves):
+    A = fem.assemble(prob)
+    B = fem.rhs(prob, waves)
+    if A.shape[0] <= 6000:
+        X = solve.dense_solve(A, B)
+    else:
+        X = np.stack([solve.cocg(A, B[:, r], rtol=1e-14, maxiter=20000).x for r in range(B.shape[1])], 1)
+    return A, B, X
+
+
+@pytest.mark.parametrize("name", ["free_cube_10", "random_pec_lossy", "aniso_partial_abc", "one_element",
+                                  "thin_slab"])
+def test_fp64_solve_matches_lu(ctx, name):
+    prob, waves = CASES[name]
+    A, B, X = _lu_solution(prob, waves)
+    kappa = float(abs(np.linalg.cond(A.toarray(), 1))) if A.shape[0] <= 6000 else 1e4
+    rtol = min(1e-10, 0.1 * 1e-9 / kappa)
+    P = F.Problem(ctx, prob)
+    H, stats, st = P.solve(waves, precision=F.FEMH_FP64, rtol=rtol)
+    assert st == F.FEMH_OK, stats
+    Ho = fem.scatter_to_grid(prob, X)
+    for r in range(len(waves)):
+        err = np.linalg.norm(H[r] - Ho[r]) / np.linalg.norm(Ho[r])
+        assert err <= 1e-9, (r, err, stats[r])
+        assert stats[r]["rel_residual"] <= rtol
+        # the reported residual is the oracle's backward error of the GPU iterate
+        x = H[r][fem.Mesh(prob).node_active].reshape(-1)
+        assert abs(solve.residual(A, x, B[:, r]) - stats[r]["rel_residual"]) <= 1e-3 * rtol
+    # nodes of PEC elements only are exactly zero
+    mesh = fem.Mesh(prob)
+    assert np.all(H[:, ~mesh.node_active] == 0)
+    P.close()
+
+
+@pytest.mark.parametrize("name", ["free_cube_10", "random_pec_lossy", "sphere_shell_14"])
+def test_mixed_solve_matches_lu(ctx, name):
+    prob, waves = CASES[name]
+    A, B, X = _lu_solution(prob, waves)
+    P = F.Problem(ctx, prob)
+    H, stats, st = P.solve(waves, precision=F.FEMH_MIXED, rtol=1e-9)
+    assert st == F.FEMH_OK, stats
+    Ho = fem.scatter_to_grid(prob, X)
+    for r in range(len(waves)):
+        err = np.linalg.norm(H[r] - Ho[r]) / np.linalg.norm(Ho[r])
+        assert err <= 1e-6, (r, err, stats[r])
+        assert stats[r]["outer_iters"] >= 1
+    P.close()
+
+
+def test_solve_is_deterministic(ctx):
+    prob, waves = CASES["random_pec_lossy"]
+    P = F.Problem(ctx, prob)
+    H1, s1, _ = P.solve(waves, precision=F.FEMH_FP64, rtol=1e-10)
+    H2, s2, _ = P.solve(waves, precision=F.FEMH_FP64, rtol=1e-10)
+    np.testing.assert_array_equal(H1, H2)
+    assert [s["iters"] for s in s1] == [s["iters"] for s in s2]
+    P.close()
+
+
+def test_iteration_limit_reports_not_converged(ctx):
+    prob, waves = CASES["free_cube_10"]
+    P = F.Problem(ctx, prob)
+    H, stats, st = P.solve(waves, precision=F.FEMH_FP64, rtol=1e-12, max_iter=5, check_every=2)
+    assert st == F.FEMH_E_NOT_CONVERGED
+    assert stats[0]["iters"] == 5 and stats[0]["status"] == F.FEMH_E_NOT_CONVERGED
+    assert 0 < stats[0]["rel_residual"] < 1.5
+    P.close()
+
+
+def test_invalid_inputs_rejected_on_device_path(ctx, torch):
+    prob, _ = W.free_cube(3)
+    q, _ = W.free_cube(3)
+    q.pec[:] = 1
+    with pytest.raises(F.FemhError) as e:
+        F.Problem(ctx, q)
+    assert e.value.status == F.FEMH_E_INVALID
+    eps = torch.from_numpy(np.ascontiguousarray(prob.eps_r.reshape(-1))).cuda()
+    eps[4] = float("nan")
+    with pytest.raises(F.FemhError) as e:
+        F.Problem(ctx, prob, device_arrays={"eps_r": eps})
+    assert e.value.status == F.FEMH_E_NONFINITE
+
+
+def test_device_arrays_give_same_matrix(ctx, torch):
+    prob, waves = CASES["random_pec_lossy"]
+    Ph = F.Problem(ctx, prob)
+    dev = {"eps_r": torch.from_numpy(np.ascontiguousarray(prob.eps_r.reshape(-1))).cuda(),
+           "mu_r": torch.from_numpy(np.ascontiguousarray(prob.mu_r.reshape(-1))).cuda(),
+           "pec": torch.from_numpy(np.ascontiguousarray(prob.pec.reshape(-1))).cuda()}
+    Pd = F.Problem(ctx, prob, device_arrays=dev)
+    a, b = Ph.export_bsr(), Pd.export_bsr()
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+    Ph.close()
+    Pd.close()
+
+
+# ------------------------------------------------------------ full sizes
+def test_pec_cube_30_full_size(ctx):
+    """3-wavelength PEC-cube workload (87 186 unknowns), FP64 to 1e-8: whole
+    matrix against the oracle; backward error of the GPU solution under the
+    oracle's matrix and right-hand side."""
+    prob, waves = W.pec_cube(30)
+    P = F.Problem(ctx, prob)
+    assert P.n_unknowns == 87186 and P.nnzb == 729182
+    rp, ci, vals, Ag = gpu_csr(P)
+    Ao = fem.assemble(prob)
+    assert abs(Ag - Ao).max() <= 1e-13 * abs(Ao).max()
+    H, stats, st = P.solve(waves, precision=F.FEMH_FP64, rtol=1e-8)
+    assert st == F.FEMH_OK, stats
+    b = fem.rhs(prob, waves)[:, 0]
+    x = H[0][fem.Mesh(prob).node_active].reshape(-1)
+    res = solve.residual(Ao, x, b)
+    assert res <= 1e-8 * 1.001, (res, stats)
+    P.close()
+
+
+def test_sphere_shell_60_bench_configuration(ctx, torch):
+    """The benchmarked workload (60^3, PEC sphere + dielectric shell, 644 136
+    unknowns) in the benchmark's launch configuration: sampled block rows
+    against the oracle's one-row assembly, sampled SpMV rows in both
+    precisions, and the mixed solve's backward error to 1e-6 under the
+    oracle's full matrix."""
+    prob, waves = W.pec_sphere_shell(60)
+    P = F.Problem(ctx, prob)
+    assert P.n_unknowns == 644136 and P.nnzb == 5561948
+    rp, ci, vals = P.export_bsr()
+    rng = np.random.default_rng(9)
+    mesh = fem.Mesh(prob)
+    rows = list(rng.choice(P.n_nodes, size=40, replace=False)) + [0, P.n_nodes - 1]
+    # rows on the PEC surface and in the dielectric shell
+    X = mesh.node_coords()
+    r = np.linalg.norm(X - 3.0, axis=1)
+    near = np.nonzero((r > 1.35) & (r < 1.95))[0]
+    rows += list(rng.choice(near, size=12, replace=False))
+    orows = fem.assemble_rows(prob, rows)
+    scale = max(abs(b).max() for r in orows.values() for b in r.values())
+    for a in rows:
+        cols = ci[rp[a]:rp[a + 1]]
+        assert sorted(orows[a]) == list(cols)
+        for k, c in enumerate(cols):
+            assert abs(vals[rp[a] + k] - orows[a][c]).max() <= 1e-13 * scale
+    # SpMV in the launch configuration the benchmark times
+    x = _randvec(rng, P.n_unknowns)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.zeros_like(xt)
+    P.spmv_dev(xt, yt, precision=F.FEMH_FP64, reps=3)
+    y = yt.cpu().numpy()
+    xt32 = xt.to(torch.complex64)
+    yt32 = torch.zeros_like(xt32)
+    P.spmv_dev(xt32, yt32, precision=F.FEMH_MIXED, reps=3)
+    y32 = yt32.cpu().numpy().astype(np.complex128)
+    x32 = x.astype(np.complex64).astype(np.complex128)
+    for a in rows:
+        yo = np.zeros(3, np.complex128)
+        bnd = np.zeros(3)
+        yo32 = np.zeros(3, np.complex128)
+        bnd32 = np.zeros(3)
+        for c, blk in orows[a].items():
+            yo += blk @ x[3 * c:3 * c + 3]
+            bnd += abs(blk) @ abs(x[3 * c:3 * c + 3])
+            b32 = blk.astype(np.complex64).astype(np.complex128)
+            yo32 += b32 @ x32[3 * c:3 * c + 3]
+            bnd32 += abs(b32) @ abs(x32[3 * c:3 * c + 3])
+        assert np.all(abs(y[3 * a:3 * a + 3] - yo) <= 1e-13 * bnd)
+        assert np.all(abs(y32[3 * a:3 * a + 3] - yo32) <= 2e-6 * bnd32)
+    # mixed-precision solve to an FP64 residual of 1e-6
+    out = torch.zeros(P.grid_shape(1), dtype=torch.complex128, device="cuda")
+    stats, st = P.solve_dev(waves, out, precision=F.FEMH_MIXED, rtol=1e-6)
+    assert st == F.FEMH_OK, stats
+    Ao = fem.assemble(prob)
+    b = fem.rhs(prob, waves)[:, 0]
+    H = out.cpu().numpy()
+    xg = H[0][mesh.node_active].reshape(-1)
+    res = solve.residual(Ao, xg, b)
+    assert res <= 1e-6 * 1.001, (res, stats)
+    P.close()

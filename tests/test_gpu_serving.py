@@ -1,0 +1,92 @@
+"""GPU tests of the continuous-batching server.
+
+A request's field is bit-for-bit the same alone, in a mix of requests of
+different sizes that overlap on the device, and through femh_solve with the
+same options; cancellation and memory admission behave as documented."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_0704_2344_amd import femh as F
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def _requests(seed, count, n_hi=18):
+    rng = np.random.default_rng(seed)
+    return [W.serving_request(rng, n_lo=8, n_hi=n_hi, nrhs_hi=3) for _ in range(count)]
+
+
+def _shape(prob, nrhs):
+    return (nrhs, prob.nz + 1, prob.ny + 1, prob.nx + 1, 3)
+
+
+def test_result_same_alone_and_in_mix(ctx):
+    prob, waves = _requests(1, 1)[0]
+    opts = dict(precision=F.FEMH_MIXED, rtol=1e-6)
+    srv = F.Server(ctx, max_slots=8, chunk_iters=16)
+    t = srv.submit(prob, waves, **opts)
+    st, alone, stats = srv.poll(t, len(waves), _shape(prob, len(waves)))
+    assert st == F.FEMH_OK, stats
+    # the same request again, in the middle of a mix
+    others = _requests(2, 6)
+    tickets = [srv.submit(p, w, **opts) for p, w in others[:3]]
+    t2 = srv.submit(prob, waves, **opts)
+    tickets += [srv.submit(p, w, **opts) for p, w in others[3:]]
+    st2, mixed, stats2 = srv.poll(t2, len(waves), _shape(prob, len(waves)))
+    assert st2 == F.FEMH_OK
+    np.testing.assert_array_equal(alone, mixed)
+    for (p, w), tk in zip(others, tickets):
+        s, _, _ = srv.poll(tk, len(w), _shape(p, len(w)))
+        assert s == F.FEMH_OK
+    rep = srv.report()
+    assert rep["completed"] == 8 and rep["failed"] == 0
+    assert rep["p99_seconds"] >= rep["p50_seconds"] > 0
+    srv.close()
+    # and the same through the plain solve path
+    P = F.Problem(ctx, prob)
+    H, s3, st3 = P.solve(waves, check_every=16, **opts)
+    assert st3 == F.FEMH_OK
+    np.testing.assert_array_equal(H, alone)
+    P.close()
+
+
+def test_cancel_and_admission(ctx):
+    big, wbig = W.pec_sphere_batched(n=30, radius=0.8, nrhs=2, seed=9)
+    small = _requests(3, 3, n_hi=12)
+    srv = F.Server(ctx, max_slots=4, chunk_iters=16)
+    tb = srv.submit(big, wbig, precision=F.FEMH_MIXED, rtol=1e-8)
+    ts = [srv.submit(p, w, precision=F.FEMH_MIXED, rtol=1e-6) for p, w in small]
+    assert srv.cancel(tb) == F.FEMH_OK
+    st, _, _ = srv.poll(tb, 2, None, want_field=False)
+    assert st == F.FEMH_E_CANCELLED
+    for (p, w), t in zip(small, ts):
+        s, _, _ = srv.poll(t, len(w), _shape(p, len(w)))
+        assert s == F.FEMH_OK
+    assert srv.cancel(123456) == F.FEMH_E_NOT_FOUND
+    srv.close()
+    # a budget that holds one small request at a time still serves them all,
+    # and a request larger than the budget is refused at submission
+    srv = F.Server(ctx, hbm_budget_bytes=64 << 20, max_slots=4)
+    with pytest.raises(F.FemhError) as e:
+        srv.submit(big, wbig)
+    assert e.value.status == F.FEMH_E_OOM
+    ts = [srv.submit(p, w, precision=F.FEMH_MIXED, rtol=1e-6) for p, w in small]
+    for (p, w), t in zip(small, ts):
+        s, _, _ = srv.poll(t, len(w), None, want_field=False)
+        assert s == F.FEMH_OK
+    rep = srv.report()
+    assert rep["peak_resident_bytes"] <= 64 << 20
+    assert rep["rejected"] == 1 and rep["completed"] == 3
+    srv.close()
