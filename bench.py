@@ -1,17 +1,27 @@
 """Benchmark: whole scattering solves per second on one MI355X.
 
-One step = one pass of the whole hot path on the 60^3 PEC-sphere +
-dielectric-shell workload (644 136 complex unknowns) with its inputs already
-in HBM: ingest + numbering + block pattern + assembly (FP64 and complex64
-values, Jacobi), right-hand side, mixed-precision solve (complex64 COCG
-with FP32 accumulation inside FP64 iterative refinement) to an FP64
-relative residual of 1e-6, and the scatter of H to the grid.
+Headline workload: the 3-wavelength cube (30^3 hexahedra, 10 nodes per
+wavelength) around a centred PEC cube of one wavelength, ABC on all outer
+faces, one plane wave of seeded direction/polarisation, FP64 solve to a
+relative residual of 1e-8 (87 186 complex unknowns, 729 182 3x3 blocks).
 
-Printed (one JSON line): solves/s of the mixed solver (value), the same
-steps with the FP64 solver for comparison, step latency p50/p99, the
-complex64 block SpMV's achieved bandwidth from HIP events around every
-product launched in the timed region (roofline), and the CPU oracle timed
-on a bounded sample of the same workload (cpu_baseline).
+One step = the whole hot path with the inputs already in HBM: ingest,
+numbering, block pattern, assembly (FP64 + complex64 values + Jacobi),
+right-hand side, COCG solve, scatter of H to the grid.
+
+Also printed on the same JSON line:
+  at_1e6        the same steps to 1e-6 with the FP64, mixed (complex64
+                vectors) and matrix-mixed (complex64 matrix, complex128
+                vectors) solvers: solves/s, iterations, p50/p99 latency
+  spmv_hbm      block SpMV bandwidth on the 60^3 PEC-sphere + dielectric
+                shell matrix (845 MB complex128, 434 MB complex64: larger
+                than the 256 MB Infinity Cache)
+  batched       the 40^3 PEC-sphere workload with 64 right-hand sides as one
+                batched complex64 solve to 1e-6 (RHS/s)
+  roofline      the dominant kernel of the timed steps (the FP64 block SpMV
+                fused with p^T A p), timed with HIP events around every
+                launch in the timed region
+  cpu_baseline  the CPU oracle on a bounded sample of the headline workload
 """
 import argparse
 import json
@@ -27,17 +37,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E datasheet
 
 
-def spmv_bytes(nn, nnzb, cbytes):
+def spmv_bytes(nn, nnzb, val_bytes, vec_bytes):
     """Algorithmic bytes of one block SpMV: every 3x3 block (9 complex values
     + one int32 column index) read once, the row pointers, x read once and y
     written once."""
-    return nnzb * (9 * cbytes + 4) + 4 * (nn + 1) + 2 * 3 * nn * cbytes
+    return nnzb * (9 * val_bytes + 4) + 4 * (nn + 1) + 2 * 3 * nn * vec_bytes
 
 
 def cpu_baseline(prob, waves, iters_needed, sample_iters):
-    """The oracle as it stands (assembly + RHS + COCG), timed on a bounded
-    sample: the full assembly and RHS, then `sample_iters` COCG iterations;
-    the solve time is extrapolated to `iters_needed` iterations."""
+    """The oracle as it stands (assembly + RHS + COCG), on a bounded sample:
+    the full assembly and RHS, then `sample_iters` COCG iterations; the solve
+    is extrapolated to `iters_needed` iterations."""
     from threadpoolctl import threadpool_limits
 
     from oracle import fem, solve
@@ -53,24 +63,24 @@ def cpu_baseline(prob, waves, iters_needed, sample_iters):
     per_iter = (t3 - t2) / sample_iters
     total = (t1 - t0) + (t2 - t1) + iters_needed * per_iter
     return {"value": 1.0 / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"full oracle assembly ({t1 - t0:.1f} s) and RHS ({t2 - t1:.2f} s) of the same workload, "
+            "sample": (f"full oracle assembly ({t1 - t0:.2f} s) and RHS ({t2 - t1:.3f} s) of the headline workload, "
                        f"then {sample_iters} FP64 COCG-Jacobi iterations ({per_iter * 1e3:.1f} ms each), "
-                       f"extrapolated to the {iters_needed} iterations the FP64 solve needs; one thread")}
+                       f"extrapolated to the {iters_needed} iterations of the GPU FP64 solve; one thread")}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64-steps", type=int, default=2)
-    ap.add_argument("--workload", default="pec_sphere_shell_60")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cmp-steps", type=int, default=3, help="steps per solver in the 1e-6 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=40)
+    ap.add_argument("--no-extras", action="store_true", help="skip the 1e-6 comparison, HBM SpMV and batched legs")
+    ap.add_argument("--cpu-sample-iters", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
-              f"described but not built", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}); the multi-GPU path is a design "
+              f"only and is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -78,72 +88,50 @@ def main():
     import workloads as W
     from paper_0704_2344_amd import femh as F
 
-    prob, waves = W.WORKLOADS[args.workload]()
-    waves = waves[:1]
     dev = torch.device("cuda", 0)
     ctx = F.Context(0)
+    prob, waves = W.pec_cube(30)
     arrays = {"eps_r": torch.from_numpy(np.ascontiguousarray(prob.eps_r.reshape(-1))).to(dev),
               "mu_r": torch.from_numpy(np.ascontiguousarray(prob.mu_r.reshape(-1))).to(dev),
               "pec": torch.from_numpy(np.ascontiguousarray(prob.pec.reshape(-1))).to(dev)}
     out = torch.zeros((1, prob.nz + 1, prob.ny + 1, prob.nx + 1, 3), dtype=torch.complex128, device=dev)
-
     info = {}
 
-    def step(precision):
+    def step(precision, rtol):
         P = F.Problem(ctx, prob, device_arrays=arrays)
-        stats, st = P.solve_dev(waves, out, precision=precision, rtol=1e-6)
+        stats, st = P.solve_dev(waves, out, precision=precision, rtol=rtol)
         if st != F.FEMH_OK:
             raise RuntimeError(f"solve failed: {stats}")
         info.update(nn=P.n_nodes, nnzb=P.nnzb, n=P.n_unknowns)
         P.close()
         return stats[0]
 
-    for _ in range(args.warmup):
-        step(F.FEMH_MIXED)
-    torch.cuda.synchronize()
+    def timed(precision, rtol, steps):
+        lat = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = None
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            last = step(precision, rtol)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - s0)
+        el = time.perf_counter() - t0
+        return steps / el, el, lat, last
 
-    # ---- timed: mixed precision (the value)
+    for _ in range(args.warmup):
+        step(F.FEMH_FP64, 1e-8)
+
+    # ---- timed headline steps, every product bracketed by HIP events
     ctx.profile(True)
     ctx.profile_read(reset=True)
-    lat = []
-    mixed_stats = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        mixed_stats = step(F.FEMH_MIXED)
-        lat.append(time.perf_counter() - s0)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    value, elapsed, lat, st64 = timed(F.FEMH_FP64, 1e-8, args.steps)
     sec, cnt = ctx.profile_read(reset=True)
-    elapsed = t1 - t0
-    value = args.steps / elapsed
-
-    # ---- same steps with the FP64 solver
-    fp64_stats = None
-    fp64_t = 0.0
-    f64_sec, f64_cnt = [0, 0, 0], [0, 0, 0]
-    if args.fp64_steps > 0:
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        for _ in range(args.fp64_steps):
-            fp64_stats = step(F.FEMH_FP64)
-        torch.cuda.synchronize()
-        fp64_t = time.perf_counter() - a
-        f64_sec, f64_cnt = ctx.profile_read(reset=True)
     ctx.profile(False)
-
     nn, nnzb = info["nn"], info["nnzb"]
-    b64 = spmv_bytes(nn, nnzb, 8)
-    avg64 = sec[1] / max(cnt[1], 1)
-    achieved = b64 / avg64 / 1e9
-    b128 = spmv_bytes(nn, nnzb, 16)
-    avg128 = f64_sec[0] / max(f64_cnt[0], 1) if f64_cnt[0] else float("nan")
-    copy_gbps = ctx.bw_probe(1 << 30, 10)
-
-    lat_sorted = sorted(lat)
-    p50 = float(np.percentile(lat_sorted, 50))
-    p99 = float(np.percentile(lat_sorted, 99))
+    b128 = spmv_bytes(nn, nnzb, 16, 16)
+    avg = sec[0] / max(cnt[0], 1)
+    achieved = b128 / avg / 1e9
 
     result = {
         "metric": "block SpMV GB/s (% HBM peak); solves/s + p99 latency at 1e-6, mixed vs FP64",
@@ -156,30 +144,75 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 inner / f64 refinement",
+        "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: 60^3 hex, PEC sphere R=1.5 wavelengths + eps_r~U[2,4] shell, "
-                               f"{info['n']} complex unknowns, {nnzb} 3x3 blocks, mixed precision to 1e-6",
+        "config": {"workload": ("pec_cube_30: 3-wavelength cube, 30^3 hexahedra, centred PEC cube of one "
+                                "wavelength, ABC outer faces, one seeded plane wave, FP64 COCG-Jacobi to 1e-8; "
+                                f"{info['n']} complex unknowns, {nnzb} 3x3 blocks"),
                    "global_batch": 1, "parallelism": "single GPU"},
-        "p50_s": p50,
-        "p99_s": p99,
-        "mixed": {"iters": mixed_stats["iters"], "outer": mixed_stats["outer_iters"],
-                  "rel_residual": mixed_stats["rel_residual"], "solve_s": mixed_stats["seconds"]},
-        "fp64": None if fp64_stats is None else {
-            "solves_per_s": args.fp64_steps / fp64_t, "iters": fp64_stats["iters"],
-            "restarts": fp64_stats["outer_iters"], "rel_residual": fp64_stats["rel_residual"],
-            "solve_s": fp64_stats["seconds"],
-            "spmv_c128_gbps": b128 / avg128 / 1e9 if f64_cnt[0] else None},
-        "mixed_vs_fp64": None if fp64_stats is None else value / (args.fp64_steps / fp64_t),
+        "p50_s": float(np.percentile(lat, 50)),
+        "p99_s": float(np.percentile(lat, 99)),
+        "solve": {"iters": st64["iters"], "restarts": st64["outer_iters"], "rel_residual": st64["rel_residual"],
+                  "solve_s": st64["seconds"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "k_cocg_spmv_dot<float> (complex64 block SpMV + fused dots)",
-                     "bytes_per_launch": b64, "avg_launch_s": avg64, "launches": cnt[1]},
-        "measured_copy_gbps": copy_gbps,
+                     "kernel": "k_cocg_spmv_dot<double> (complex128 block SpMV + p^T A p)",
+                     "bytes_per_launch": b128, "avg_launch_s": avg, "launches": cnt[0],
+                     "note": "the 111 MB complex128 matrix fits the 256 MB Infinity Cache"},
     }
+
+    if not args.no_extras:
+        cmp = {}
+        for name, prec in (("fp64", F.FEMH_FP64), ("mixed", F.FEMH_MIXED), ("mixed_matrix", F.FEMH_MIXED_MATRIX)):
+            step(prec, 1e-6)
+            sps, el, lt, s = timed(prec, 1e-6, args.cmp_steps)
+            cmp[name] = {"solves_per_s": sps, "iters": s["iters"], "updates": s["outer_iters"],
+                         "rel_residual": s["rel_residual"], "p50_s": float(np.percentile(lt, 50)),
+                         "p99_s": float(np.percentile(lt, 99))}
+        cmp["best_mixed_vs_fp64"] = max(cmp["mixed"]["solves_per_s"], cmp["mixed_matrix"]["solves_per_s"]) / \
+            cmp["fp64"]["solves_per_s"]
+        result["at_1e6"] = cmp
+
+        # block SpMV on a matrix larger than the Infinity Cache
+        p2, _ = W.pec_sphere_shell(60)
+        P2 = F.Problem(ctx, p2)
+        n2 = P2.n_unknowns
+        x = torch.randn(n2, dtype=torch.complex128, device=dev)
+        y = torch.zeros_like(x)
+        x32 = x.to(torch.complex64)
+        y32 = torch.zeros_like(x32)
+        hb = {}
+        for name, prec, xx, yy, vb, xb in (("c128", F.FEMH_FP64, x, y, 16, 16),
+                                           ("c64", F.FEMH_MIXED, x32, y32, 8, 8),
+                                           ("c64_matrix_c128_vectors", F.FEMH_MIXED_MATRIX, x, y, 8, 16)):
+            P2.spmv_dev(xx, yy, prec, reps=3)
+            t = P2.spmv_dev(xx, yy, prec, reps=20)
+            gb = spmv_bytes(P2.n_nodes, P2.nnzb, vb, xb) / t / 1e9
+            hb[name] = {"us": t * 1e6, "GBps": gb, "frac_hbm_peak": gb / HBM_PEAK_GBPS}
+        hb["workload"] = f"pec_sphere_shell_60 matrix: {n2} unknowns, {P2.nnzb} blocks"
+        hb["copy_probe_GBps"] = ctx.bw_probe(1 << 30, 10)
+        result["spmv_hbm"] = hb
+        P2.close()
+
+        # batched right-hand sides
+        p3, w3 = W.pec_sphere_batched(40)
+        P3 = F.Problem(ctx, p3)
+        o3 = torch.zeros(P3.grid_shape(64), dtype=torch.complex128, device=dev)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        stats3, st3 = P3.solve_dev(w3, o3, batched=True, precision=F.FEMH_MIXED, rtol=1e-6)
+        torch.cuda.synchronize()
+        el3 = time.perf_counter() - a
+        its = [s["iters"] for s in stats3]
+        result["batched"] = {"workload": "pec_sphere_40_b64: 40^3, PEC sphere R=1 wavelength, 64 RHS, to 1e-6",
+                             "status": st3, "rhs_per_s": 64 / el3, "seconds": el3,
+                             "iters_min": min(its), "iters_max": max(its),
+                             "max_rel_residual": max(s["rel_residual"] for s in stats3),
+                             "spmm_tile": P3.spmm_tile()}
+        P3.close()
+
     if not args.no_cpu_baseline:
-        iters_needed = fp64_stats["iters"] if fp64_stats else mixed_stats["iters"]
-        result["cpu_baseline"] = cpu_baseline(prob, waves, iters_needed, args.cpu_sample_iters)
+        result["cpu_baseline"] = cpu_baseline(prob, waves, st64["iters"], args.cpu_sample_iters)
     print(json.dumps(result))
 
 

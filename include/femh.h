@@ -70,8 +70,11 @@ typedef enum {
 enum { FEMH_FACE_ABC = 0,      /* eq. (3) absorbing condition */
        FEMH_FACE_NATURAL = 1   /* no surface term (a PEC wall for H) */ };
 
-typedef enum { FEMH_FP64 = 0,  /* complex128 Krylov solve */
-               FEMH_MIXED = 1  /* complex64 inner COCG, FP64 refinement */ } femh_precision;
+typedef enum { FEMH_FP64 = 0,          /* complex128 matrix and Krylov vectors */
+               FEMH_MIXED = 1,         /* complex64 matrix and Krylov vectors (FP32 arithmetic),
+                                          reliable updates into an FP64 iterate */
+               FEMH_MIXED_MATRIX = 2   /* complex64 matrix, complex128 Krylov vectors,
+                                          reliable updates against the FP64 matrix */ } femh_precision;
 
 typedef enum { FEMH_PRECOND_JACOBI = 0,  /* z = D^-1 r, D = diag(A) (section 3.1.5.1) */
                FEMH_PRECOND_NONE = 1 } femh_precond;
@@ -113,7 +116,8 @@ typedef struct {
   int32_t precond;       /* femh_precond; default Jacobi */
   double rtol;           /* stop at ||b - A x||_2 <= rtol ||b||_2 (FP64 true residual); default 1e-6 */
   int32_t max_iter;      /* Krylov iterations in total (inner ones for MIXED); default 50000 */
-  double inner_rtol;     /* MIXED: relative reduction asked of each inner solve; default 1e-5 */
+  double inner_rtol;     /* MIXED*: residual reduction between reliable updates; default 0.1
+                            (FEMH_MIXED), 1e-3 (FEMH_MIXED_MATRIX) */
   int32_t max_outer;     /* MIXED: refinement steps; default 20 */
   int32_t check_every;   /* iterations queued between host convergence reads; default 32 */
 } femh_solve_opts;
@@ -221,7 +225,8 @@ int femh_export_rhs(femh_problem* prob, int32_t nrhs, const femh_plane_wave* wav
 int femh_export_jacobi(const femh_problem* prob, femh_c128* dinv);
 
 /* y = A x on device vectors of n_unknowns complex entries: complex128 for
- * FEMH_FP64, complex64 with FP32 accumulation for FEMH_MIXED.  The product
+ * FEMH_FP64, complex64 with FP32 accumulation for FEMH_MIXED, the complex64
+ * matrix times complex128 vectors for FEMH_MIXED_MATRIX.  The product
  * runs `reps` >= 1 times; *avg_seconds (may be NULL) receives the mean
  * kernel time measured with HIP events on the context's stream. */
 int femh_spmv_dev(femh_problem* prob, int32_t precision, const void* x_dev, void* y_dev,
@@ -248,11 +253,12 @@ int femh_bw_probe(femh_ctx* ctx, int64_t bytes, int32_t reps, double* gbps);
 
 /* Per-kernel event timing of the solvers.  When enabled, every solve
  * records HIP events around each matrix product it launches; the totals
- * accumulate until read.  *spmv_seconds / *spmv_launches receive the sum
- * of kernel times and the number of products that did work, per
- * precision (index 0 = FP64, 1 = complex64, 2 = batched SpMM). */
+ * accumulate until read.  spmv_seconds / spmv_launches receive the sum of
+ * kernel times and the number of products that did work, per kind (index
+ * 0 = FP64, 1 = complex64, 2 = batched SpMM, 3 = complex64 matrix with
+ * complex128 vectors). */
 int femh_profile_enable(femh_ctx* ctx, int32_t on);
-int femh_profile_read(femh_ctx* ctx, double spmv_seconds[3], int64_t spmv_launches[3],
+int femh_profile_read(femh_ctx* ctx, double spmv_seconds[4], int64_t spmv_launches[4],
                       int32_t reset);
 
 /* --------------------------------------------------------------- serving */

@@ -130,7 +130,7 @@ int femh_estimate_bytes(const femh_problem_desc* desc, int32_t nrhs, int32_t pre
     femh::set_error("%s", m.c_str());
     return st;
   }
-  if (!bytes || nrhs < 0 || (precision != FEMH_FP64 && precision != FEMH_MIXED)) {
+  if (!bytes || nrhs < 0 || (precision != FEMH_FP64 && precision != FEMH_MIXED && precision != FEMH_MIXED_MATRIX)) {
     femh::set_error("bad estimate arguments");
     return FEMH_E_INVALID;
   }
@@ -195,7 +195,7 @@ int femh_solve_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* wave
     return st;
   }
   const femh_solve_opts o = femh::opts_with_defaults(opts);
-  if (o.precision != FEMH_FP64 && o.precision != FEMH_MIXED) {
+  if (o.precision != FEMH_FP64 && o.precision != FEMH_MIXED && o.precision != FEMH_MIXED_MATRIX) {
     femh::set_error("unknown precision %d", o.precision);
     return FEMH_E_INVALID;
   }
@@ -428,7 +428,8 @@ int femh_export_jacobi(const femh_problem* p, femh_c128* dinv) {
 
 int femh_spmv_dev(femh_problem* p, int32_t precision, const void* x, void* y, int32_t reps, double* avg_seconds) {
   femh::clear_error();
-  if (!p || !x || !y || reps < 1 || (precision != FEMH_FP64 && precision != FEMH_MIXED)) {
+  if (!p || !x || !y || reps < 1 ||
+      (precision != FEMH_FP64 && precision != FEMH_MIXED && precision != FEMH_MIXED_MATRIX)) {
     femh::set_error("bad spmv arguments");
     return FEMH_E_INVALID;
   }
@@ -440,6 +441,8 @@ int femh_spmv_dev(femh_problem* p, int32_t precision, const void* x, void* y, in
   for (int i = 0; i < reps; ++i) {
     if (precision == FEMH_FP64)
       FEMH_TRY_HIP(femh::k::spmv_c128(c->stream, p->pat, p->val64, (const double2*)x, (double2*)y, p->spmv));
+    else if (precision == FEMH_MIXED_MATRIX)
+      FEMH_TRY_HIP(femh::k::spmv_m32(c->stream, p->pat, p->val32, (const double2*)x, (double2*)y, p->spmv));
     else
       FEMH_TRY_HIP(femh::k::spmv_c64(c->stream, p->pat, p->val32, (const float2*)x, (float2*)y, p->spmv));
   }
@@ -491,12 +494,12 @@ int femh_profile_enable(femh_ctx* c, int32_t on) {
   return FEMH_OK;
 }
 
-int femh_profile_read(femh_ctx* c, double sec[3], int64_t cnt[3], int32_t reset) {
+int femh_profile_read(femh_ctx* c, double sec[4], int64_t cnt[4], int32_t reset) {
   if (!c || !sec || !cnt) {
     femh::set_error("NULL argument");
     return FEMH_E_INVALID;
   }
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 4; ++i) {
     sec[i] = c->prof_sec[i];
     cnt[i] = c->prof_cnt[i];
     if (reset) {

@@ -61,23 +61,26 @@ struct PatternDev {
 };
 
 // COCG scalar block of one right-hand side, kept on the device so the
-// host never waits inside an iteration.  Complex numbers as double2.
+// host never waits inside an iteration.  Values that the iteration kernels
+// both read and write are kept in two slots indexed by the parity of the
+// iteration (a kernel argument), so no workgroup of a launch can observe a
+// value another workgroup of the same launch writes.  Complex as double2.
 struct CocgScalars {
-  double2 rho;        // r^T z
-  double2 pq;         // p^T A p
-  double2 alpha, beta;
-  double rr;          // ||r||^2 (recursive)
-  double bb;          // ||b||^2 of the system being solved
-  double tol2;        // stop when rr <= tol2 * bb
-  double bd_tol;      // breakdown threshold (relative)
-  double rr_max;      // largest ||r||^2 since the last reliable update
-  double delta2;      // > 0: stop with done = 4 once rr <= delta2 * rr_max
-  int32_t iters;      // iterations done
-  int32_t max_iters;  // stop (not converged) at this count
-  int32_t done;       // 0 running, 1 converged, 2 iteration limit, 3 breakdown,
-                      // 4 residual dropped by delta: reliable update due
-  int32_t pad;
-  uint32_t ticket[4]; // last-block counters of the reduction kernels
+  double2 rho[2];      // r^T z of the current iterate, slot = parity
+  double2 alpha, beta; // last step (beta also feeds cocg_pupdate_*)
+  double rr;           // ||r||^2 after the last iteration (host view)
+  double bb;           // ||b||^2 of the system being solved
+  double tol2;         // stop when rr <= tol2 * bb
+  double bd_tol;       // breakdown threshold (relative)
+  double rr_max[2];    // largest ||r||^2 since the last reliable update, slot = parity
+  double delta2;       // > 0: stop with done = 4 once rr <= delta2 * rr_max
+  int32_t iters[2];    // iterations done, slot = parity
+  int32_t max_iters;   // stop (not converged) at this count
+  int32_t done;        // 0 running, 1 converged, 2 iteration limit, 3 breakdown,
+                       // 4 residual dropped by delta: reliable update due
+  int32_t iters_out;   // iterations done (host view)
+  int32_t stop_par;    // slot of rho_{k-1} when the recurrence stopped
+  uint32_t ticket[4];  // last-block counters of the once-per-segment kernels
 };
 
 // Per-column COCG scalars of a batched solve (up to 64 columns).  done[c]:
@@ -170,38 +173,64 @@ hipError_t spmv_c128(hipStream_t st, const PatternDev& p, const double2* val, co
 hipError_t spmv_c64(hipStream_t st, const PatternDev& p, const float2* val, const float2* x,
                     float2* y, SpmvLaunch L);
 
-// COCG building blocks.  Partials hold 2 * blocks doubles (or double2).
+// complex64 matrix times complex128 vector (values promoted, FP64 sums)
+hipError_t spmv_m32(hipStream_t st, const PatternDev& p, const float2* val, const double2* x,
+                    double2* y, SpmvLaunch L);
+
+// COCG building blocks.  One iteration = spmv_dot (q = A p, per-workgroup
+// partials of p^T q), update (every workgroup re-reduces those partials in
+// a fixed order for alpha; x += alpha p, r -= alpha q; partials of r^T z,
+// ||r||^2) and pupdate (re-reduces them: convergence / limit / breakdown /
+// reliable-update decisions, beta, p = z + beta p).  `par` is the parity of
+// the iteration (the host counts the iterations it queues); segment-start
+// kernels write slot `par` of the iteration that follows them.  Partials
+// hold 4 doubles per workgroup of the producing kernel.
 hipError_t cocg_init_c128(hipStream_t st, int64_t n, const double2* b, const double2* dinv,
-                          double2* x, double2* r, double2* p, CocgScalars* sc, double2* partials,
-                          int zero_x);
+                          double2* x, double2* r, double2* p, CocgScalars* sc, void* partials,
+                          int zero_x, int par);
 hipError_t cocg_spmv_dot_c128(hipStream_t st, const PatternDev& pt, const double2* val,
-                              const double2* p, double2* q, CocgScalars* sc, double2* partials,
+                              const double2* p, double2* q, CocgScalars* sc, void* partials,
                               SpmvLaunch L);
+hipError_t cocg_spmv_dot_m32(hipStream_t st, const PatternDev& pt, const float2* val,
+                             const double2* p, double2* q, CocgScalars* sc, void* partials,
+                             SpmvLaunch L);
 hipError_t cocg_update_c128(hipStream_t st, int64_t n, const double2* dinv, double2* x,
                             double2* r, const double2* p, const double2* q, CocgScalars* sc,
-                            double2* partials);
+                            const void* partials_in, int nin, void* partials_out, int par);
 hipError_t cocg_pupdate_c128(hipStream_t st, int64_t n, const double2* dinv, const double2* r,
-                             double2* p, const CocgScalars* sc);
+                             double2* p, CocgScalars* sc, const void* partials_in, int par);
+// p = D^-1 r + beta p with beta from the scalar block (after a reliable update)
+hipError_t cocg_apply_beta_c128(hipStream_t st, int64_t n, const double2* dinv, const double2* r,
+                                double2* p, const CocgScalars* sc);
 
-// complex64 recurrence; its reductions accumulate in FP64 (partials hold
-// 4 doubles per workgroup)
 hipError_t cocg_spmv_dot_c64(hipStream_t st, const PatternDev& pt, const float2* val,
                              const float2* p, float2* q, CocgScalars* sc, void* partials,
                              SpmvLaunch L);
 hipError_t cocg_update_c64(hipStream_t st, int64_t n, const float2* dinv, float2* x, float2* r,
-                           const float2* p, const float2* q, CocgScalars* sc, void* partials);
+                           const float2* p, const float2* q, CocgScalars* sc,
+                           const void* partials_in, int nin, void* partials_out, int par);
 hipError_t cocg_pupdate_c64(hipStream_t st, int64_t n, const float2* dinv, const float2* r,
-                            float2* p, const CocgScalars* sc);
+                            float2* p, CocgScalars* sc, const void* partials_in, int par);
+hipError_t cocg_apply_beta_c64(hipStream_t st, int64_t n, const float2* dinv, const float2* r,
+                               float2* p, const CocgScalars* sc);
+// workgroups of the update kernel (= partial count seen by pupdate)
+int update_blocks_for(int64_t n);
 
 // Reliable update of the complex64 recurrence: r = r64 * inv_s, z = D^-1 r;
 // rho' = r^T z.  fresh = 1: p = z (restart).  fresh = 0: beta = rho' /
-// (rho * ratio) for the direction kept in the old scaling (ratio = s_old /
-// s_new); the caller then runs cocg_pupdate_c64.  Sets tol2, clears done.
+// (rho_{k-1} * ratio) for the direction kept in the old scaling (ratio =
+// s_old / s_new); the caller then runs cocg_apply_beta_c64.  Writes slot
+// `par`, sets tol2, clears done.
 hipError_t cocg_rescale_c64(hipStream_t st, int64_t n, const double2* r64, double inv_s,
                             const float2* dinv, float2* r, float2* p, CocgScalars* sc,
-                            void* partials, double ratio, double tol2, int fresh);
+                            void* partials, double ratio, double tol2, int fresh, int par);
 // x64 += s * d32 and d32 = 0
 hipError_t ir_fold(hipStream_t st, int64_t n, float2* d, double s, double2* x);
+// FP64 reliable update after r was overwritten with the true residual:
+// rho' = r^T D^-1 r, beta = rho' / rho_{k-1}; the caller runs
+// cocg_apply_beta_c128.  Writes slot `par`.
+hipError_t cocg_replace_c128(hipStream_t st, int64_t n, const double2* r, const double2* dinv,
+                             CocgScalars* sc, void* partials, int par);
 
 // r = b - A x (FP64) and ||r||^2 -> *rr_out (device), deterministic.
 hipError_t residual_c128(hipStream_t st, const PatternDev& pt, const double2* val,
@@ -223,8 +252,8 @@ struct Ctx {
   femh_allocator alloc{};
   int n_cu = 256;
   bool profile = false;
-  double prof_sec[3] = {0, 0, 0};
-  int64_t prof_cnt[3] = {0, 0, 0};
+  double prof_sec[4] = {0, 0, 0, 0};
+  int64_t prof_cnt[4] = {0, 0, 0, 0};
   std::vector<hipEvent_t> ev_pool;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   void* pinned = nullptr;  // small pinned host buffer for scalar readback

@@ -17,9 +17,12 @@
 // sweep a contiguous window of rows at a time, keeping the x gathers inside
 // one L2.
 //
-// Reductions are deterministic: each workgroup writes a partial, and the
-// last workgroup to finish (device-scope ticket) sums the partials in a
-// fixed order and updates the scalar block.  No floating-point atomics.
+// Reductions are deterministic and the iteration kernels use no atomics and
+// no device-scope fences: each workgroup writes a partial sum, and the next
+// kernel's workgroups each re-reduce all partials in one fixed order (the
+// totals are bit-identical everywhere).  Once-per-segment kernels (start,
+// reliable update, true residual) let the last workgroup to finish (a
+// device-scope ticket) reduce instead.  No floating-point atomics.
 #include "internal.h"
 
 namespace femh {
@@ -57,8 +60,10 @@ __device__ __forceinline__ R shfl_down_z(R v, int off, int lane) {
 // y_i of NR block rows in lanes 0, 3, 6 (see file comment).  The rows'
 // load chains are interleaved so a wave keeps NR rows of loads in flight.
 // rows[] are wave-uniform; rows >= nn contribute nothing.
-template <typename R, int NR>
-__device__ __forceinline__ void rows_product(const PatternDev& p, const typename Cx<R>::T* __restrict__ val,
+// VC is the stored value type (complex64 values are promoted to R in the
+// product when the vectors are complex128).
+template <typename R, int NR, typename VC = typename Cx<R>::T>
+__device__ __forceinline__ void rows_product(const PatternDev& p, const VC* __restrict__ val,
                                              const typename Cx<R>::T* __restrict__ x, const int32_t (&rows)[NR],
                                              int lane, R (&yr)[NR], R (&yi)[NR]) {
   using C = typename Cx<R>::T;
@@ -77,7 +82,7 @@ __device__ __forceinline__ void rows_product(const PatternDev& p, const typename
     }
     if (lane >= 63) nb[k] = 0;
   }
-  C a[NR][4];
+  VC a[NR][4];
   int32_t c[NR][4];
 #pragma unroll
   for (int k = 0; k < NR; ++k)
@@ -99,8 +104,9 @@ __device__ __forceinline__ void rows_product(const PatternDev& p, const typename
       const int b = bo + 7 * kk;
       if (b < nb[k]) {
         const C xv = x[3 * (size_t)c[k][kk] + j];
-        ar[k] += a[k][kk].x * xv.x - a[k][kk].y * xv.y;
-        ai[k] += a[k][kk].x * xv.y + a[k][kk].y * xv.x;
+        const R vr = (R)a[k][kk].x, vi = (R)a[k][kk].y;
+        ar[k] += vr * xv.x - vi * xv.y;
+        ai[k] += vr * xv.y + vi * xv.x;
       }
     }
   }
@@ -133,10 +139,10 @@ __device__ __forceinline__ int wave_row_start(int& nwaves) {
   return __builtin_amdgcn_readfirstlane((xcd * per_xcd + loc) * kWavesPerBlock + wib);
 }
 
-constexpr int kRowsPerWave = 2;  // rows a wave keeps in flight
+constexpr int kRowsPerWave = 1;  // rows a wave keeps in flight (2 costs occupancy: measured slower)
 
-template <typename R>
-__global__ void __launch_bounds__(kBlock) k_spmv(PatternDev p, const typename Cx<R>::T* __restrict__ val,
+template <typename R, typename VC = typename Cx<R>::T>
+__global__ void __launch_bounds__(kBlock) k_spmv(PatternDev p, const VC* __restrict__ val,
                                                  const typename Cx<R>::T* __restrict__ x,
                                                  typename Cx<R>::T* __restrict__ y) {
   using C = typename Cx<R>::T;
@@ -148,7 +154,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(PatternDev p, const typename Cx
 #pragma unroll
     for (int k = 0; k < kRowsPerWave; ++k) rows[k] = r0 + k * nwaves;
     R yr[kRowsPerWave], yi[kRowsPerWave];
-    rows_product<R, kRowsPerWave>(p, val, x, rows, lane, yr, yi);
+    rows_product<R, kRowsPerWave, VC>(p, val, x, rows, lane, yr, yi);
     if (lane == 0 || lane == 3 || lane == 6) {
 #pragma unroll
       for (int k = 0; k < kRowsPerWave; ++k)
@@ -224,8 +230,9 @@ __device__ __forceinline__ bool last_block_total(R (&v)[NV], R* __restrict__ par
 }
 
 // ----------------------------------------------------------------- COCG
-// Scalar-block updates after each reduction.  All in FP64 (the complex64
-// path converts its FP32 totals).
+// Scalar-block arithmetic is FP64 throughout; the complex64 recurrence
+// accumulates its reductions in FP64 too (products of two floats are exact
+// in double), since the unconjugated form r^T z cancels heavily.
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   const double s = fmax(fabs(b.x), fabs(b.y));
   const double br = b.x / s, bi = b.y / s;
@@ -234,23 +241,49 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 }
 __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 
-// init: r = src (optionally x = 0), p = D^-1 r; rho = r^T p, rr = ||r||^2, zz = ||p||^2
+// Per-workgroup partials of 4 sums -> partials[block][4] (plain stores; the
+// consumer is a later kernel).
+__device__ __forceinline__ void store_partials4(double (&v)[4], double* __restrict__ partials) {
+  block_sum<double, 4>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) partials[(size_t)blockIdx.x * 4 + i] = v[i];
+  }
+}
+
+// Every workgroup re-reduces the producer's nin partials in one fixed order,
+// so all workgroups (and every run) see bit-identical totals.
+__device__ __forceinline__ void reduce_partials4(const double* __restrict__ partials, int nin, double (&t)[4]) {
+  __shared__ double s_tot[4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nin; b += kBlock)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += partials[(size_t)b * 4 + i];
+  block_sum<double, 4>(acc);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s_tot[i] = acc[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t[i] = s_tot[i];
+}
+
+// Segment start: r = src (optionally x = 0), p = D^-1 r; rho = r^T p into
+// slot par, rr, zz.  One writer (last workgroup).
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_cocg_init(int64_t n, const double2* __restrict__ src64,
                                                       const typename Cx<R>::T* __restrict__ dinv,
                                                       typename Cx<R>::T* __restrict__ x,
                                                       typename Cx<R>::T* __restrict__ r,
                                                       typename Cx<R>::T* __restrict__ p, CocgScalars* sc,
-                                                      double* __restrict__ partials, int zero_x, const double* src_rr) {
+                                                      double* __restrict__ partials, int zero_x, int par) {
   using C = typename Cx<R>::T;
   if (sc->done) return;
-  // the complex64 inner solve starts from the FP64 residual scaled to unit norm
-  const double scale = src_rr ? 1.0 / sqrt(*src_rr) : 1.0;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     const double2 s = src64[i];
-    C ri = mk<C>(s.x * scale, s.y * scale);
+    C ri = mk<C>(s.x, s.y);
     const C di = dinv[i];
     C zi;
     zi.x = di.x * ri.x - di.y * ri.y;
@@ -266,21 +299,24 @@ __global__ void __launch_bounds__(kBlock) k_cocg_init(int64_t n, const double2* 
   block_sum<double, 4>(v);
   if (!last_block_total<double, 4>(v, partials, &sc->ticket[0])) return;
   if (threadIdx.x == 0) {
-    const double2 rho = make_double2((double)v[0], (double)v[1]);
-    const double rr = (double)v[2], zz = (double)v[3];
-    sc->rho = rho;
+    const double2 rho = make_double2(v[0], v[1]);
+    const double rr = v[2], zz = v[3];
+    sc->rho[par] = rho;
     sc->rr = rr;
-    if (src_rr || sc->bb <= 0.0) sc->bb = rr;
+    sc->rr_max[par] = rr;
+    sc->iters[par] = sc->iters_out;
+    if (sc->bb <= 0.0) sc->bb = rr;
     if (rr <= sc->tol2 * sc->bb) sc->done = 1;
     else if (cabs2(rho) <= sc->bd_tol * sc->bd_tol * rr * zz) sc->done = 3;
+    if (sc->done) sc->stop_par = par;
   }
 }
 
-// q = A p and p^T q, ||p||^2, ||q||^2; last block: alpha = rho / p^T q
-template <typename R>
-__global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const typename Cx<R>::T* __restrict__ val,
+// q = A p; partials of p^T q (re, im), ||p||^2, ||q||^2.  No scalar writes.
+template <typename R, typename VC = typename Cx<R>::T>
+__global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const VC* __restrict__ val,
                                                           const typename Cx<R>::T* __restrict__ p,
-                                                          typename Cx<R>::T* __restrict__ q, CocgScalars* sc,
+                                                          typename Cx<R>::T* __restrict__ q, const CocgScalars* sc,
                                                           double* __restrict__ partials) {
   using C = typename Cx<R>::T;
   if (sc->done) return;
@@ -293,7 +329,7 @@ __global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const t
 #pragma unroll
     for (int k = 0; k < kRowsPerWave; ++k) rows[k] = r0 + k * nwaves;
     R yr[kRowsPerWave], yi[kRowsPerWave];
-    rows_product<R, kRowsPerWave>(pt, val, p, rows, lane, yr, yi);
+    rows_product<R, kRowsPerWave, VC>(pt, val, p, rows, lane, yr, yi);
     if (lane == 0 || lane == 3 || lane == 6) {
 #pragma unroll
       for (int k = 0; k < kRowsPerWave; ++k) {
@@ -311,31 +347,35 @@ __global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const t
       }
     }
   }
-  block_sum<double, 4>(v);
-  if (!last_block_total<double, 4>(v, partials, &sc->ticket[1])) return;
-  if (threadIdx.x == 0) {
-    const double2 pq = make_double2((double)v[0], (double)v[1]);
-    sc->pq = pq;
-    if (cabs2(pq) <= sc->bd_tol * sc->bd_tol * (double)v[2] * (double)v[3]) {
-      sc->done = 3;
-    } else {
-      sc->alpha = cdiv(sc->rho, pq);
-    }
-  }
+  store_partials4(v, partials);
 }
 
-// x += alpha p; r -= alpha q; z = D^-1 r (not stored); rho' = r^T z, ||r||^2, ||z||^2.
-// Last block: convergence / iteration limit / breakdown, beta = rho' / rho.
+// alpha = rho / p^T q (re-reduced); x += alpha p; r -= alpha q;
+// partials of rho' = r^T z (z = D^-1 r, not stored), ||r||^2, ||z||^2.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t n, const typename Cx<R>::T* __restrict__ dinv,
                                                         typename Cx<R>::T* __restrict__ x,
                                                         typename Cx<R>::T* __restrict__ r,
                                                         const typename Cx<R>::T* __restrict__ p,
                                                         const typename Cx<R>::T* __restrict__ q, CocgScalars* sc,
-                                                        double* __restrict__ partials) {
+                                                        const double* __restrict__ pin, int nin,
+                                                        double* __restrict__ pout, int par) {
   using C = typename Cx<R>::T;
   if (sc->done) return;
-  const R ar = (R)sc->alpha.x, ai = (R)sc->alpha.y;
+  double t[4];
+  reduce_partials4(pin, nin, t);
+  const double2 pq = make_double2(t[0], t[1]);
+  if (cabs2(pq) <= sc->bd_tol * sc->bd_tol * t[2] * t[3]) {
+    // every workgroup reaches the same verdict; one records it
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->done = 3;
+      sc->stop_par = par;
+    }
+    return;
+  }
+  const double2 alpha = cdiv(sc->rho[par], pq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->alpha = alpha;
+  const R ar = (R)alpha.x, ai = (R)alpha.y;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
@@ -354,34 +394,88 @@ __global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t n, const typenam
     v[2] += (double)ri.x * ri.x + (double)ri.y * ri.y;
     v[3] += (double)zr * zr + (double)zi * zi;
   }
-  block_sum<double, 4>(v);
-  if (!last_block_total<double, 4>(v, partials, &sc->ticket[2])) return;
-  if (threadIdx.x == 0) {
-    const double2 rho_new = make_double2((double)v[0], (double)v[1]);
-    const double rr = (double)v[2], zz = (double)v[3];
-    sc->iters += 1;
-    sc->rr = rr;
-    if (rr <= sc->tol2 * sc->bb) {
-      sc->done = 1;
-    } else if (sc->iters >= sc->max_iters) {
-      sc->done = 2;
-    } else if (cabs2(rho_new) <= sc->bd_tol * sc->bd_tol * rr * zz) {
-      sc->done = 3;
-    } else {
-      bool trigger = false;
-      if (sc->delta2 > 0.0) {
-        if (rr > sc->rr_max) sc->rr_max = rr;
-        else trigger = rr <= sc->delta2 * sc->rr_max;
-      }
-      if (trigger) {
-        // keep rho = rho_{k-1}: the reliable update recomputes rho_k from the
-        // replaced residual and the direction update follows from it
-        sc->done = 4;
-      } else {
-        sc->beta = cdiv(rho_new, sc->rho);
-        sc->rho = rho_new;
-      }
+  store_partials4(v, pout);
+}
+
+// Re-reduce rho', ||r||^2, ||z||^2; decide (converged / iteration limit /
+// breakdown / reliable update due) identically in every workgroup; if the
+// recurrence continues, beta = rho' / rho and p = z + beta p.  Workgroup 0
+// records the outcome; values read here live in slot par, values written
+// for the next iteration in slot par ^ 1.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cocg_pupdate(int64_t n, const typename Cx<R>::T* __restrict__ dinv,
+                                                         const typename Cx<R>::T* __restrict__ r,
+                                                         typename Cx<R>::T* __restrict__ p, CocgScalars* sc,
+                                                         const double* __restrict__ pin, int nin, int par) {
+  using C = typename Cx<R>::T;
+  if (sc->done) return;
+  double t[4];
+  reduce_partials4(pin, nin, t);
+  const double2 rho_new = make_double2(t[0], t[1]);
+  const double rr = t[2], zz = t[3];
+  const int it = sc->iters[par] + 1;
+  const double rmax = sc->rr_max[par];
+  int stop = 0;
+  if (rr <= sc->tol2 * sc->bb) stop = 1;
+  else if (it >= sc->max_iters) stop = 2;
+  else if (cabs2(rho_new) <= sc->bd_tol * sc->bd_tol * rr * zz) stop = 3;
+  else if (sc->delta2 > 0.0 && rr <= rmax && rr <= sc->delta2 * rmax) stop = 4;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (stop) {
+    // rho_{k-1} stays in slot par for the reliable update
+    if (lead) {
+      sc->iters[par ^ 1] = it;
+      sc->iters_out = it;
+      sc->rr = rr;
+      sc->stop_par = par;
+      sc->done = stop;
     }
+    return;
+  }
+  const double2 beta = cdiv(rho_new, sc->rho[par]);
+  if (lead) {
+    sc->rho[par ^ 1] = rho_new;
+    sc->rr_max[par ^ 1] = rr > rmax ? rr : rmax;
+    sc->iters[par ^ 1] = it;
+    sc->iters_out = it;
+    sc->rr = rr;
+    sc->beta = beta;
+  }
+  const R br = (R)beta.x, bi = (R)beta.y;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const C di = dinv[i], ri = r[i];
+    C pi = p[i];
+    const R zr = di.x * ri.x - di.y * ri.y;
+    const R zi = di.x * ri.y + di.y * ri.x;
+    const R nr = zr + br * pi.x - bi * pi.y;
+    const R ni = zi + br * pi.y + bi * pi.x;
+    pi.x = nr;
+    pi.y = ni;
+    p[i] = pi;
+  }
+}
+
+// p = D^-1 r + beta p with beta from the scalar block (after a reliable
+// update that kept the direction).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cocg_apply_beta(int64_t n, const typename Cx<R>::T* __restrict__ dinv,
+                                                            const typename Cx<R>::T* __restrict__ r,
+                                                            typename Cx<R>::T* __restrict__ p, const CocgScalars* sc) {
+  using C = typename Cx<R>::T;
+  if (sc->done) return;
+  const R br = (R)sc->beta.x, bi = (R)sc->beta.y;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const C di = dinv[i], ri = r[i];
+    C pi = p[i];
+    const R zr = di.x * ri.x - di.y * ri.y;
+    const R zi = di.x * ri.y + di.y * ri.x;
+    const R nr = zr + br * pi.x - bi * pi.y;
+    const R ni = zi + br * pi.y + bi * pi.x;
+    pi.x = nr;
+    pi.y = ni;
+    p[i] = pi;
   }
 }
 
@@ -390,7 +484,7 @@ __global__ void __launch_bounds__(kBlock) k_cocg_rescale(int64_t n, const double
                                                          const float2* __restrict__ dinv, float2* __restrict__ r,
                                                          float2* __restrict__ p, CocgScalars* sc,
                                                          double* __restrict__ partials, double ratio, double tol2,
-                                                         int fresh) {
+                                                         int fresh, int par) {
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
@@ -409,19 +503,56 @@ __global__ void __launch_bounds__(kBlock) k_cocg_rescale(int64_t n, const double
   block_sum<double, 4>(v);
   if (!last_block_total<double, 4>(v, partials, &sc->ticket[3])) return;
   if (threadIdx.x == 0) {
-    const double2 rho_new = make_double2((double)v[0], (double)v[1]);
-    const double rr = (double)v[2], zz = (double)v[3];
+    const double2 rho_new = make_double2(v[0], v[1]);
+    const double rr = v[2], zz = v[3];
     sc->tol2 = tol2;
     sc->rr = rr;
-    sc->rr_max = rr;
+    sc->rr_max[par] = rr;
+    sc->iters[par] = sc->iters_out;
     sc->done = 0;
     if (cabs2(rho_new) <= sc->bd_tol * sc->bd_tol * rr * zz) {
       sc->done = 3;
+      sc->stop_par = par;
     } else if (!fresh) {
-      const double2 den = make_double2(sc->rho.x * ratio, sc->rho.y * ratio);
-      sc->beta = cdiv(rho_new, den);
+      const double2 old = sc->rho[sc->stop_par];
+      sc->beta = cdiv(rho_new, make_double2(old.x * ratio, old.y * ratio));
     }
-    sc->rho = rho_new;
+    sc->rho[par] = rho_new;
+  }
+}
+
+// Reliable update of an FP64 recurrence whose residual buffer has just been
+// overwritten with the true residual: rho' = r^T D^-1 r, beta = rho' /
+// rho_{k-1} (the caller then applies beta to the direction).
+__global__ void __launch_bounds__(kBlock) k_cocg_replace(int64_t n, const double2* __restrict__ r,
+                                                         const double2* __restrict__ dinv, CocgScalars* sc,
+                                                         double* __restrict__ partials, int par) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double2 ri = r[i], di = dinv[i];
+    const double zr = di.x * ri.x - di.y * ri.y;
+    const double zi = di.x * ri.y + di.y * ri.x;
+    v[0] += ri.x * zr - ri.y * zi;
+    v[1] += ri.x * zi + ri.y * zr;
+    v[2] += ri.x * ri.x + ri.y * ri.y;
+    v[3] += zr * zr + zi * zi;
+  }
+  block_sum<double, 4>(v);
+  if (!last_block_total<double, 4>(v, partials, &sc->ticket[3])) return;
+  if (threadIdx.x == 0) {
+    const double2 rho_new = make_double2(v[0], v[1]);
+    sc->rr = v[2];
+    sc->rr_max[par] = v[2];
+    sc->iters[par] = sc->iters_out;
+    sc->done = 0;
+    if (cabs2(rho_new) <= sc->bd_tol * sc->bd_tol * v[2] * v[3]) {
+      sc->done = 3;
+      sc->stop_par = par;
+    } else {
+      sc->beta = cdiv(rho_new, sc->rho[sc->stop_par]);
+    }
+    sc->rho[par] = rho_new;
   }
 }
 
@@ -435,28 +566,6 @@ __global__ void __launch_bounds__(kBlock) k_ir_fold(int64_t n, float2* __restric
     xi.y += s * (double)di.y;
     x[i] = xi;
     d[i] = make_float2(0.f, 0.f);
-  }
-}
-
-// p = D^-1 r + beta p
-template <typename R>
-__global__ void __launch_bounds__(kBlock) k_cocg_pupdate(int64_t n, const typename Cx<R>::T* __restrict__ dinv,
-                                                         const typename Cx<R>::T* __restrict__ r,
-                                                         typename Cx<R>::T* __restrict__ p, const CocgScalars* sc) {
-  using C = typename Cx<R>::T;
-  if (sc->done) return;
-  const R br = (R)sc->beta.x, bi = (R)sc->beta.y;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-    const C di = dinv[i], ri = r[i];
-    C pi = p[i];
-    const R zr = di.x * ri.x - di.y * ri.y;
-    const R zi = di.x * ri.y + di.y * ri.x;
-    const R nr = zr + br * pi.x - bi * pi.y;
-    const R ni = zi + br * pi.y + bi * pi.x;
-    pi.x = nr;
-    pi.y = ni;
-    p[i] = pi;
   }
 }
 
@@ -535,6 +644,27 @@ hipError_t spmv_c128(hipStream_t st, const PatternDev& p, const double2* val, co
   return hipGetLastError();
 }
 
+hipError_t spmv_m32(hipStream_t st, const PatternDev& p, const float2* val, const double2* x, double2* y,
+                    SpmvLaunch L) {
+  if (p.nn == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_spmv<double, float2>), dim3(L.blocks), dim3(kBlock), 0, st, p, val, x, y);
+  return hipGetLastError();
+}
+
+hipError_t cocg_spmv_dot_m32(hipStream_t st, const PatternDev& pt, const float2* val, const double2* p, double2* q,
+                             CocgScalars* sc, void* partials, SpmvLaunch L) {
+  hipLaunchKernelGGL((k_cocg_spmv_dot<double, float2>), dim3(L.blocks), dim3(kBlock), 0, st, pt, val, p, q, sc,
+                     reinterpret_cast<double*>(partials));
+  return hipGetLastError();
+}
+
+hipError_t cocg_replace_c128(hipStream_t st, int64_t n, const double2* r, const double2* dinv, CocgScalars* sc,
+                             void* partials, int par) {
+  hipLaunchKernelGGL(k_cocg_replace, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, r, dinv, sc,
+                     reinterpret_cast<double*>(partials), par);
+  return hipGetLastError();
+}
+
 hipError_t spmv_c64(hipStream_t st, const PatternDev& p, const float2* val, const float2* x, float2* y,
                     SpmvLaunch L) {
   if (p.nn == 0) return hipSuccess;
@@ -542,57 +672,73 @@ hipError_t spmv_c64(hipStream_t st, const PatternDev& p, const float2* val, cons
   return hipGetLastError();
 }
 
+int update_blocks_for(int64_t n) { return reduce_blocks_for(n); }
+
 hipError_t cocg_init_c128(hipStream_t st, int64_t n, const double2* b, const double2* dinv, double2* x, double2* r,
-                          double2* p, CocgScalars* sc, double2* partials, int zero_x) {
+                          double2* p, CocgScalars* sc, void* partials, int zero_x, int par) {
   hipLaunchKernelGGL(k_cocg_init<double>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, b, dinv, x, r, p, sc,
-                     reinterpret_cast<double*>(partials), zero_x, (const double*)nullptr);
+                     reinterpret_cast<double*>(partials), zero_x, par);
   return hipGetLastError();
 }
 
 hipError_t cocg_spmv_dot_c128(hipStream_t st, const PatternDev& pt, const double2* val, const double2* p, double2* q,
-                              CocgScalars* sc, double2* partials, SpmvLaunch L) {
-  hipLaunchKernelGGL(k_cocg_spmv_dot<double>, dim3(L.blocks), dim3(kBlock), 0, st, pt, val, p, q, sc,
+                              CocgScalars* sc, void* partials, SpmvLaunch L) {
+  hipLaunchKernelGGL((k_cocg_spmv_dot<double>), dim3(L.blocks), dim3(kBlock), 0, st, pt, val, p, q, sc,
                      reinterpret_cast<double*>(partials));
   return hipGetLastError();
 }
 
 hipError_t cocg_update_c128(hipStream_t st, int64_t n, const double2* dinv, double2* x, double2* r, const double2* p,
-                            const double2* q, CocgScalars* sc, double2* partials) {
+                            const double2* q, CocgScalars* sc, const void* pin, int nin, void* pout, int par) {
   hipLaunchKernelGGL(k_cocg_update<double>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, x, r, p, q, sc,
-                     reinterpret_cast<double*>(partials));
+                     reinterpret_cast<const double*>(pin), nin, reinterpret_cast<double*>(pout), par);
   return hipGetLastError();
 }
 
 hipError_t cocg_pupdate_c128(hipStream_t st, int64_t n, const double2* dinv, const double2* r, double2* p,
-                             const CocgScalars* sc) {
-  hipLaunchKernelGGL(k_cocg_pupdate<double>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, r, p, sc);
+                             CocgScalars* sc, const void* pin, int par) {
+  hipLaunchKernelGGL(k_cocg_pupdate<double>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, r, p, sc,
+                     reinterpret_cast<const double*>(pin), reduce_blocks_for(n), par);
+  return hipGetLastError();
+}
+
+hipError_t cocg_apply_beta_c128(hipStream_t st, int64_t n, const double2* dinv, const double2* r, double2* p,
+                                const CocgScalars* sc) {
+  hipLaunchKernelGGL(k_cocg_apply_beta<double>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, r, p, sc);
   return hipGetLastError();
 }
 
 hipError_t cocg_spmv_dot_c64(hipStream_t st, const PatternDev& pt, const float2* val, const float2* p, float2* q,
                              CocgScalars* sc, void* partials, SpmvLaunch L) {
-  hipLaunchKernelGGL(k_cocg_spmv_dot<float>, dim3(L.blocks), dim3(kBlock), 0, st, pt, val, p, q, sc,
+  hipLaunchKernelGGL((k_cocg_spmv_dot<float>), dim3(L.blocks), dim3(kBlock), 0, st, pt, val, p, q, sc,
                      reinterpret_cast<double*>(partials));
   return hipGetLastError();
 }
 
 hipError_t cocg_update_c64(hipStream_t st, int64_t n, const float2* dinv, float2* x, float2* r, const float2* p,
-                           const float2* q, CocgScalars* sc, void* partials) {
+                           const float2* q, CocgScalars* sc, const void* pin, int nin, void* pout, int par) {
   hipLaunchKernelGGL(k_cocg_update<float>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, x, r, p, q, sc,
-                     reinterpret_cast<double*>(partials));
+                     reinterpret_cast<const double*>(pin), nin, reinterpret_cast<double*>(pout), par);
   return hipGetLastError();
 }
 
 hipError_t cocg_pupdate_c64(hipStream_t st, int64_t n, const float2* dinv, const float2* r, float2* p,
-                            const CocgScalars* sc) {
-  hipLaunchKernelGGL(k_cocg_pupdate<float>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, r, p, sc);
+                            CocgScalars* sc, const void* pin, int par) {
+  hipLaunchKernelGGL(k_cocg_pupdate<float>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, r, p, sc,
+                     reinterpret_cast<const double*>(pin), reduce_blocks_for(n), par);
+  return hipGetLastError();
+}
+
+hipError_t cocg_apply_beta_c64(hipStream_t st, int64_t n, const float2* dinv, const float2* r, float2* p,
+                               const CocgScalars* sc) {
+  hipLaunchKernelGGL(k_cocg_apply_beta<float>, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, dinv, r, p, sc);
   return hipGetLastError();
 }
 
 hipError_t cocg_rescale_c64(hipStream_t st, int64_t n, const double2* r64, double inv_s, const float2* dinv, float2* r,
-                            float2* p, CocgScalars* sc, void* partials, double ratio, double tol2, int fresh) {
+                            float2* p, CocgScalars* sc, void* partials, double ratio, double tol2, int fresh, int par) {
   hipLaunchKernelGGL(k_cocg_rescale, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, r64, inv_s, dinv, r, p, sc,
-                     reinterpret_cast<double*>(partials), ratio, tol2, fresh);
+                     reinterpret_cast<double*>(partials), ratio, tol2, fresh, par);
   return hipGetLastError();
 }
 

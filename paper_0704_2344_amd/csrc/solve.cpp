@@ -11,6 +11,11 @@
 // FP64 true residual b - A x is formed and, if it does not meet it, COCG
 // restarts from it.
 //
+// Matrix-mixed mode: the FP64 COCG recurrence with the complex64 matrix in
+// the product (values promoted, FP64 sums); reliable updates against the
+// FP64 matrix replace the recursive residual by the true one (keeping the
+// direction) whenever it has fallen by inner_rtol.
+//
 // Mixed mode: the COCG recurrence runs on the complex64 matrix and
 // complex64 vectors, on a residual scaled to unit norm.  When its recursive
 // residual has fallen by inner_rtol since the last update (or meets the
@@ -56,13 +61,15 @@ struct Stepper {
   const double2* b = nullptr;
   double2* x = nullptr;
   femh_solve_opts o{};
-  bool mixed = false;
+  bool mixed = false;  // complex64 vectors and matrix
+  bool m32 = false;    // complex64 matrix, complex128 vectors
   int64_t n = 0;
   std::vector<void*> owned;
   // device workspace
   double2 *r64 = nullptr, *p64 = nullptr, *q64 = nullptr;
   float2 *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
-  void* partials = nullptr;
+  void* partials = nullptr;  // SpMV -> update partials; also once-per-segment kernels
+  void* partials_b = nullptr;  // update -> direction-update partials
   CocgScalars* sc = nullptr;
   Aux* aux = nullptr;
   const double2* dinv64 = nullptr;
@@ -119,6 +126,7 @@ struct Stepper {
     x = x_dev;
     o = opts;
     mixed = o.precision == FEMH_MIXED;
+    m32 = o.precision == FEMH_MIXED_MATRIX;
     n = 3 * (int64_t)P->pat.nn;
     r64 = (double2*)dev(16 * n);
     if (!r64) return oom();
@@ -134,9 +142,10 @@ struct Stepper {
       if (!p64 || !q64) return oom();
     }
     partials = dev(8 * kPartialSlots);
+    partials_b = dev(8 * kPartialSlots);
     sc = (CocgScalars*)dev(sizeof(CocgScalars));
     aux = (Aux*)dev(sizeof(Aux));
-    if (!partials || !sc || !aux) return oom();
+    if (!partials || !partials_b || !sc || !aux) return oom();
     dinv64 = P->dinv64;
     dinv32 = P->dinv32;
     if (o.precond == FEMH_PRECOND_NONE) {
@@ -178,8 +187,12 @@ struct Stepper {
     return FEMH_OK;
   }
 
+  int par() const { return launches & 1; }
+
   int queue_iteration() {
     const bool prof = c->profile;
+    const int pr = par();
+    const int nin = P->spmv.blocks;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
       e0 = pool_event(c, 2 * (size_t)launches);
@@ -193,13 +206,16 @@ struct Stepper {
     if (mixed) {
       FEMH_TRY_HIP(k::cocg_spmv_dot_c64(s, P->pat, P->val32, p32, q32, sc, partials, P->spmv));
       if (prof) FEMH_TRY_HIP(hipEventRecord(e1, s));
-      FEMH_TRY_HIP(k::cocg_update_c64(s, n, dinv32, x32, r32, p32, q32, sc, partials));
-      FEMH_TRY_HIP(k::cocg_pupdate_c64(s, n, dinv32, r32, p32, sc));
+      FEMH_TRY_HIP(k::cocg_update_c64(s, n, dinv32, x32, r32, p32, q32, sc, partials, nin, partials_b, pr));
+      FEMH_TRY_HIP(k::cocg_pupdate_c64(s, n, dinv32, r32, p32, sc, partials_b, pr));
     } else {
-      FEMH_TRY_HIP(k::cocg_spmv_dot_c128(s, P->pat, P->val64, p64, q64, sc, (double2*)partials, P->spmv));
+      if (m32)
+        FEMH_TRY_HIP(k::cocg_spmv_dot_m32(s, P->pat, P->val32, p64, q64, sc, partials, P->spmv));
+      else
+        FEMH_TRY_HIP(k::cocg_spmv_dot_c128(s, P->pat, P->val64, p64, q64, sc, partials, P->spmv));
       if (prof) FEMH_TRY_HIP(hipEventRecord(e1, s));
-      FEMH_TRY_HIP(k::cocg_update_c128(s, n, dinv64, x, r64, p64, q64, sc, (double2*)partials));
-      FEMH_TRY_HIP(k::cocg_pupdate_c128(s, n, dinv64, r64, p64, sc));
+      FEMH_TRY_HIP(k::cocg_update_c128(s, n, dinv64, x, r64, p64, q64, sc, partials, nin, partials_b, pr));
+      FEMH_TRY_HIP(k::cocg_pupdate_c128(s, n, dinv64, r64, p64, sc, partials_b, pr));
     }
     ++launches;
     return FEMH_OK;
@@ -256,13 +272,14 @@ struct Stepper {
       hw->delta2 = o.inner_rtol * o.inner_rtol;
       FEMH_TRY_HIP(hipMemcpyAsync(sc, hw, sizeof(*hw), hipMemcpyHostToDevice, s));
       FEMH_TRY_HIP(k::cocg_rescale_c64(s, n, r64, 1.0 / scale, dinv32, r32, p32, sc, partials, 1.0,
-                                       o.rtol * o.rtol * bb / (scale * scale), 1));
+                                       o.rtol * o.rtol * bb / (scale * scale), 1, par()));
     } else {
       hw->tol2 = o.rtol * o.rtol;
       hw->bb = bb;
       hw->bd_tol = 1e-14;
+      if (m32) hw->delta2 = o.inner_rtol * o.inner_rtol;
       FEMH_TRY_HIP(hipMemcpyAsync(sc, hw, sizeof(*hw), hipMemcpyHostToDevice, s));
-      FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, (double2*)partials, 0));
+      FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, partials, 0, par()));
     }
     new_segment(0);
     return FEMH_OK;
@@ -271,8 +288,8 @@ struct Stepper {
   // the recurrence stopped: fold (mixed) and form the FP64 true residual
   int on_stop(const CocgScalars& st) {
     last_done = st.done;
-    iters = st.iters;
-    collect_profile(st.iters);
+    iters = st.iters_out;
+    collect_profile(st.iters_out);
     if (mixed) FEMH_TRY_HIP(k::ir_fold(s, n, x32, scale, x));
     FEMH_TRY(queue_residual());
     phase = WAIT_CHECK;
@@ -284,7 +301,7 @@ struct Stepper {
     ++outer;
     if (rel <= o.rtol) return finish(FEMH_OK);
     if (last_done == 2 || iters >= o.max_iter || !std::isfinite(rel)) return finish(FEMH_E_NOT_CONVERGED);
-    const int cap = mixed ? std::max(o.max_outer, 1) * 50 : std::max(o.max_outer, 1);
+    const int cap = (mixed || m32) ? std::max(o.max_outer, 1) * 50 : std::max(o.max_outer, 1);
     if (outer > cap) return finish(last_done == 3 ? FEMH_E_BREAKDOWN : FEMH_E_NOT_CONVERGED);
     if (last_done == 3 && iters == seg_iters && outer > 1) return finish(FEMH_E_BREAKDOWN);
     if (mixed) {
@@ -292,9 +309,13 @@ struct Stepper {
       const double ns = std::sqrt(ha->rr);
       const int fresh = last_done == 3 ? 1 : 0;
       FEMH_TRY_HIP(k::cocg_rescale_c64(s, n, r64, 1.0 / ns, dinv32, r32, p32, sc, partials, scale / ns,
-                                       o.rtol * o.rtol * bb / (ns * ns), fresh));
-      if (!fresh) FEMH_TRY_HIP(k::cocg_pupdate_c64(s, n, dinv32, r32, p32, sc));
+                                       o.rtol * o.rtol * bb / (ns * ns), fresh, par()));
+      if (!fresh) FEMH_TRY_HIP(k::cocg_apply_beta_c64(s, n, dinv32, r32, p32, sc));
       scale = ns;
+    } else if (m32 && last_done != 3) {
+      // r64 now holds the true residual: keep the direction
+      FEMH_TRY_HIP(k::cocg_replace_c128(s, n, r64, dinv64, sc, partials, par()));
+      FEMH_TRY_HIP(k::cocg_apply_beta_c128(s, n, dinv64, r64, p64, sc));
     } else {
       // restart COCG from the true residual, keeping x and the iteration count
       std::memset(hw, 0, sizeof(*hw));
@@ -302,9 +323,10 @@ struct Stepper {
       hw->bb = bb;
       hw->bd_tol = 1e-14;
       hw->max_iters = o.max_iter;
-      hw->iters = iters;
+      hw->iters_out = iters;
+      if (m32) hw->delta2 = o.inner_rtol * o.inner_rtol;
       FEMH_TRY_HIP(hipMemcpyAsync(sc, hw, sizeof(*hw), hipMemcpyHostToDevice, s));
-      FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, (double2*)partials, 0));
+      FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, partials, 0, par()));
     }
     new_segment(iters);
     return FEMH_OK;
@@ -370,7 +392,7 @@ struct Stepper {
   void fill_stats(femh_solve_stats* st) const {
     st->status = status;
     st->iters = iters;
-    st->outer_iters = mixed ? outer : std::max(outer - 1, 0);
+    st->outer_iters = (mixed || m32) ? outer : std::max(outer - 1, 0);
     st->rel_residual = rel;
   }
 };
@@ -423,8 +445,9 @@ int solve_single(Problem* P, const double2* b, double2* x, const femh_solve_opts
   S->fill_stats(st);
   st->seconds = ms * 1e-3;
   if (c->profile) {
-    c->prof_sec[S->mixed ? 1 : 0] += S->prof_seconds;
-    c->prof_cnt[S->mixed ? 1 : 0] += S->prof_count;
+    const int slot = S->mixed ? 1 : (S->m32 ? 3 : 0);
+    c->prof_sec[slot] += S->prof_seconds;
+    c->prof_cnt[slot] += S->prof_count;
   }
   rc = S->status;
   delete S;

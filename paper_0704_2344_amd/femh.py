@@ -37,6 +37,7 @@ FEMH_FACE_ABC = 0
 FEMH_FACE_NATURAL = 1
 FEMH_FP64 = 0
 FEMH_MIXED = 1
+FEMH_MIXED_MATRIX = 2
 FEMH_PRECOND_JACOBI = 0
 FEMH_PRECOND_NONE = 1
 
@@ -140,7 +141,7 @@ SIGNATURES = {
     "femh_spmm_set_tile": (C.c_int, [P, I32, I32]),
     "femh_bw_probe": (C.c_int, [P, I64, I32, PD]),
     "femh_profile_enable": (C.c_int, [P, I32]),
-    "femh_profile_read": (C.c_int, [P, C.c_double * 3, C.c_int64 * 3, I32]),
+    "femh_profile_read": (C.c_int, [P, C.c_double * 4, C.c_int64 * 4, I32]),
     "femh_server_create": (C.c_int, [P, C.POINTER(femh_server_opts), C.POINTER(P)]),
     "femh_server_submit": (C.c_int, [P, C.POINTER(femh_problem_desc), I32, C.POINTER(femh_plane_wave),
                                      C.POINTER(femh_solve_opts), C.POINTER(C.c_uint64)]),
@@ -358,8 +359,8 @@ class Context:
         check(self.lib.femh_profile_enable(self.handle, 1 if on else 0))
 
     def profile_read(self, reset=True):
-        sec = (C.c_double * 3)()
-        cnt = (C.c_int64 * 3)()
+        sec = (C.c_double * 4)()
+        cnt = (C.c_int64 * 4)()
         check(self.lib.femh_profile_read(self.handle, sec, cnt, 1 if reset else 0))
         return list(sec), list(cnt)
 

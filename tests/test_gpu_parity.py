@@ -125,6 +125,11 @@ def test_spmv_matches_oracle(ctx, torch, name):
     ref = A32 @ x32.astype(np.complex128)
     bound32 = abs(A32) @ abs(x32.astype(np.complex128))
     assert np.all(abs(y32 - ref) <= 2e-6 * bound32 + 1e-30)
+    # complex64 matrix times a complex128 vector, FP64 arithmetic
+    ym = torch.zeros_like(xt)
+    P.spmv_dev(xt, ym, precision=F.FEMH_MIXED_MATRIX, reps=2)
+    ym = ym.cpu().numpy()
+    assert np.all(abs(ym - A32 @ x) <= 1e-13 * (abs(A32) @ abs(x)) + 1e-300)
     P.close()
 
 
@@ -155,19 +160,20 @@ def test_fp64_solve_matches_lu(ctx, name):
         assert stats[r]["rel_residual"] <= rtol
         # the reported residual is the oracle's backward error of the GPU iterate
         x = H[r][fem.Mesh(prob).node_active].reshape(-1)
-        assert abs(solve.residual(A, x, B[:, r]) - stats[r]["rel_residual"]) <= 1e-3 * rtol
+        assert abs(solve.residual(A, x, B[:, r]) - stats[r]["rel_residual"]) <= 0.02 * rtol
     # nodes of PEC elements only are exactly zero
     mesh = fem.Mesh(prob)
     assert np.all(H[:, ~mesh.node_active] == 0)
     P.close()
 
 
+@pytest.mark.parametrize("prec", [F.FEMH_MIXED, F.FEMH_MIXED_MATRIX])
 @pytest.mark.parametrize("name", ["free_cube_10", "random_pec_lossy", "sphere_shell_14"])
-def test_mixed_solve_matches_lu(ctx, name):
+def test_mixed_solve_matches_lu(ctx, name, prec):
     prob, waves = CASES[name]
     A, B, X = _lu_solution(prob, waves)
     P = F.Problem(ctx, prob)
-    H, stats, st = P.solve(waves, precision=F.FEMH_MIXED, rtol=1e-9)
+    H, stats, st = P.solve(waves, precision=prec, rtol=1e-9)
     assert st == F.FEMH_OK, stats
     Ho = fem.scatter_to_grid(prob, X)
     for r in range(len(waves)):
