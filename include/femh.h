@@ -199,10 +199,13 @@ int femh_solve_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* wave
                    const femh_solve_opts* opts, femh_c128* H_out_dev, femh_solve_stats* stats);
 
 /* Batched right-hand sides: the nrhs (<= 64) columns advance together,
- * one complex64 block-sparse matrix times dense block (SpMM) per
- * iteration with per-column COCG scalars, and FP64 refinement of every
- * column to opts->rtol.  Each column follows its own single-RHS
- * recurrence.  H_out_dev as in femh_solve_dev. */
+ * one block-sparse matrix times dense block (SpMM) per iteration, each
+ * column with its own COCG scalars, FP64 iterate, residual and product
+ * (directions stored in complex64), and reliable updates against the FP64
+ * matrix to opts->rtol.  opts->precision is ignored; opts->inner_rtol
+ * (default 1e-3) is the residual drop that triggers a column's update.
+ * Device memory: four FP64 and one complex64 [n_unknowns][64] blocks
+ * whatever nrhs is.  H_out_dev as in femh_solve_dev. */
 int femh_solve_batched_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves,
                            const femh_solve_opts* opts, femh_c128* H_out_dev,
                            femh_solve_stats* stats);
@@ -232,18 +235,24 @@ int femh_export_jacobi(const femh_problem* prob, femh_c128* dinv);
 int femh_spmv_dev(femh_problem* prob, int32_t precision, const void* x_dev, void* y_dev,
                   int32_t reps, double* avg_seconds);
 
-/* Y = A X for ncols (1..64) complex64 columns; X and Y are device arrays
- * [n_unknowns][ncols] (column index fastest).  Timing as femh_spmv_dev. */
+/* Y = A X for ncols (1..64) columns: X complex64 and Y complex128 device
+ * arrays [n_unknowns][ncols] (column index fastest), the batched solver's
+ * product (FP64 arithmetic on the complex128 matrix, or FP32 matrix-core
+ * products per block summed in FP64, as tuned).  Timing as femh_spmv_dev. */
 int femh_spmm_dev(femh_problem* prob, int32_t ncols, const void* X_dev, void* Y_dev,
                   int32_t reps, double* avg_seconds);
 
-/* The SpMM shape the autotuner chose for this problem (timed candidates on
- * the first batched product): *kind = 1 matrix cores, 0 vector FMAs, -1 not
+/* The SpMM shape the batched solver uses for this problem: *kind = 0 FP64
+ * vector FMAs on the complex128 matrix (the only kind the autotuner times,
+ * over grid sizes, on the first batched product), 1 matrix cores (complex64
+ * matrix, FP32 products per 3x3 block; only when set explicitly), -1 not
  * tuned yet; *blocks = workgroups of the launch. */
 int femh_spmm_tile(const femh_problem* prob, int32_t* kind, int32_t* blocks);
 
 /* Override the autotuner's choice (kind 0 or 1; blocks a positive multiple
- * of 8, at most 2048), e.g. to replay a shape tuned offline. */
+ * of 8, at most 2048), e.g. to replay a shape tuned offline.  Kind 1 is
+ * for well-conditioned systems: on indefinite ones its FP32 products can
+ * stall the batched recurrence. */
 int femh_spmm_set_tile(femh_problem* prob, int32_t kind, int32_t blocks);
 
 /* Streaming copy of `bytes` bytes between two device buffers the library

@@ -1,8 +1,11 @@
 // Host driver of the batched-RHS solve: every column runs its own COCG
-// recurrence (the single-RHS algorithm, complex64 with FP32 accumulation),
-// the columns sharing one SpMM per iteration; per-column reliable updates
-// fold the complex64 partial solutions into the FP64 iterates and restart
-// each recurrence from its FP64 true residual (same search direction).
+// recurrence, the columns sharing one SpMM per iteration.  Each column's
+// iterate, residual and product are FP64; its direction is stored in
+// complex64 (the SpMM's input).  When a column's residual has fallen by
+// inner_rtol below its largest value since the last update (or meets the
+// tolerance, or breaks down), its residual is replaced by the FP64 true
+// residual b - A x and the recurrence continues with the same direction
+// (restarts after a breakdown).
 //
 // One iteration = SpMM + per-column alpha + update + per-column beta +
 // direction update (5 kernels).  A chunk of `check_every` iterations is
@@ -53,7 +56,7 @@ int ilog2(int64_t v) {
 
 }  // namespace
 
-int autotune_spmm(Problem* P, const float2* Pv, float2* Qv, double* partials, const BatchScalars* sc) {
+int autotune_spmm(Problem* P, const float2* Pv, double2* Qv, double* partials, const BatchScalars* sc) {
   if (P->tile.kind >= 0) return FEMH_OK;
   Ctx* c = P->ctx;
   const std::pair<int, int> key(c->n_cu, ilog2(P->pat.nn));
@@ -70,17 +73,19 @@ int autotune_spmm(Problem* P, const float2* Pv, float2* Qv, double* partials, co
   hipEvent_t e0, e1;
   FEMH_TRY_HIP(hipEventCreate(&e0));
   FEMH_TRY_HIP(hipEventCreate(&e1));
+  // Only the FP64 vector kernel is a candidate: the matrix-core kernel's
+  // FP32 block products stall indefinite systems (explicit request only).
   float best = 1e30f;
-  BatchTile best_tile{1, k::batched_blocks_for(P->pat.nn, c->n_cu, 4)};
-  int best_per_cu = 4;
-  const int kinds[2] = {1, 0};
+  BatchTile best_tile{0, k::batched_blocks_for(P->pat.nn, c->n_cu, 8)};
+  int best_per_cu = 8;
+  const int kinds[1] = {0};
   const int per_cus[3] = {2, 4, 8};
   for (int kind : kinds)
     for (int pc : per_cus) {
       BatchTile t{kind, k::batched_blocks_for(P->pat.nn, c->n_cu, pc)};
-      FEMH_TRY_HIP(k::bspmm(s, P->pat, P->val32, Pv, Qv, partials, sc, t));  // warm
+      FEMH_TRY_HIP(k::bspmm(s, P->pat, P->val64, P->val32, Pv, Qv, partials, sc, t));  // warm
       FEMH_TRY_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) FEMH_TRY_HIP(k::bspmm(s, P->pat, P->val32, Pv, Qv, partials, sc, t));
+      for (int r = 0; r < 3; ++r) FEMH_TRY_HIP(k::bspmm(s, P->pat, P->val64, P->val32, Pv, Qv, partials, sc, t));
       FEMH_TRY_HIP(hipEventRecord(e1, s));
       FEMH_TRY_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -109,27 +114,25 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
   double2* B64 = (double2*)W.get(v64);
   double2* X64 = (double2*)W.get(v64);
   double2* R64 = (double2*)W.get(v64);
-  float2* X32 = (float2*)W.get(v32);
-  float2* R32 = (float2*)W.get(v32);
   float2* P32 = (float2*)W.get(v32);
-  float2* Q32 = (float2*)W.get(v32);
+  double2* Q64 = (double2*)W.get(v64);
   double* partials = (double*)W.get(kPartialBytes);
   BatchScalars* sc = (BatchScalars*)W.get(sizeof(BatchScalars));
   BatchPlan* plan = (BatchPlan*)W.get(sizeof(BatchPlan));
   double* rr64 = (double*)W.get(64 * sizeof(double));
-  if (!B64 || !X64 || !R64 || !X32 || !R32 || !P32 || !Q32 || !partials || !sc || !plan || !rr64) {
+  if (!B64 || !X64 || !R64 || !P32 || !Q64 || !partials || !sc || !plan || !rr64) {
     set_error("device allocation failed (batched workspace)");
     return FEMH_E_OOM;
   }
-  const float2* dinv = P->dinv32;
+  const double2* dinv = P->dinv64;
   if (o.precond == FEMH_PRECOND_NONE) {
-    float2* ones = (float2*)W.get(8 * n);
+    double2* ones = (double2*)W.get(16 * n);
     if (!ones) {
       set_error("device allocation failed (identity preconditioner)");
       return FEMH_E_OOM;
     }
-    std::vector<float2> h((size_t)n, make_float2(1.f, 0.f));
-    FEMH_TRY_HIP(hipMemcpyAsync(ones, h.data(), 8 * n, hipMemcpyHostToDevice, s));
+    std::vector<double2> h((size_t)n, make_double2(1.0, 0.0));
+    FEMH_TRY_HIP(hipMemcpyAsync(ones, h.data(), 16 * n, hipMemcpyHostToDevice, s));
     FEMH_TRY_HIP(hipStreamSynchronize(s));
     dinv = ones;
   }
@@ -143,10 +146,9 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
 
   FEMH_TRY_HIP(k::to_block(s, n, nrhs, b, B64));
   FEMH_TRY_HIP(hipMemsetAsync(X64, 0, v64, s));
-  FEMH_TRY_HIP(hipMemsetAsync(X32, 0, v32, s));
   FEMH_TRY_HIP(hipMemsetAsync(P32, 0, v32, s));
-  FEMH_TRY_HIP(k::bresidual64(s, P->pat, P->val64, X64, B64, R64, (double*)partials, rblocks, 64, rr64));
-  std::vector<double> hrr(64), bb(64), scale(64, 0.0);
+  FEMH_TRY_HIP(k::bresidual64(s, P->pat, P->val64, X64, B64, R64, partials, rblocks, 64, rr64, nullptr));
+  std::vector<double> hrr(64), bb(64);
   FEMH_TRY_HIP(hipMemcpyAsync(hrr.data(), rr64, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
   FEMH_TRY_HIP(hipStreamSynchronize(s));
 
@@ -158,19 +160,15 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
   std::memset(&hp, 0, sizeof(hp));
   hs->max_iters = o.max_iter;
   hs->delta2 = o.inner_rtol * o.inner_rtol;
-  hs->bd_tol = 1e-6;
+  hs->bd_tol = 1e-13;  // FP64 residual recurrence: only genuine breakdowns
   std::vector<int> updates(64, 0), final_status(64, FEMH_OK);
   std::vector<double> rel(64, 0.0);
   for (int col = 0; col < 64; ++col) {
     bb[col] = col < nrhs ? hrr[col] : 0.0;
     if (bb[col] > 0.0) {
       hs->done[col] = 0;
-      scale[col] = std::sqrt(bb[col]);
       hp.action[col] = 2;
-      hp.scale[col] = 0.0;
-      hp.inv_s[col] = 1.0 / scale[col];
-      hp.ratio[col] = 1.0;
-      hp.tol2[col] = o.rtol * o.rtol;
+      hp.tol2[col] = o.rtol * o.rtol * bb[col];
       rel[col] = 1.0;
     } else {
       hs->done[col] = 5;
@@ -179,20 +177,20 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
   }
   FEMH_TRY_HIP(hipMemcpyAsync(sc, hs, sizeof(*hs), hipMemcpyHostToDevice, s));
   FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
-  FEMH_TRY_HIP(k::brescale(s, n, R64, dinv, R32, P32, partials, vblocks, 64, sc, plan));
+  FEMH_TRY_HIP(k::brescale(s, n, R64, dinv, P32, partials, vblocks, 64, sc, plan));
   FEMH_TRY_HIP(hipStreamSynchronize(s));
-  FEMH_TRY(autotune_spmm(P, P32, Q32, partials, sc));
+  FEMH_TRY(autotune_spmm(P, P32, Q64, partials, sc));
   const BatchTile tile = P->tile;
 
   // one chunk of iterations, captured once
   auto launch_chunk = [&]() -> hipError_t {
     for (int i = 0; i < o.check_every; ++i) {
       hipError_t e;
-      if ((e = k::bspmm(s, P->pat, P->val32, P32, Q32, partials, sc, tile)) != hipSuccess) return e;
+      if ((e = k::bspmm(s, P->pat, P->val64, P->val32, P32, Q64, partials, sc, tile)) != hipSuccess) return e;
       if ((e = k::bred_alpha(s, partials, tile.blocks, 64, sc)) != hipSuccess) return e;
-      if ((e = k::bupdate(s, n, dinv, X32, R32, P32, Q32, partials, vblocks, sc)) != hipSuccess) return e;
+      if ((e = k::bupdate(s, n, dinv, X64, R64, P32, Q64, partials, vblocks, sc)) != hipSuccess) return e;
       if ((e = k::bred_beta(s, partials, vblocks, 64, sc)) != hipSuccess) return e;
-      if ((e = k::bpupdate(s, n, dinv, R32, P32, vblocks, sc, nullptr)) != hipSuccess) return e;
+      if ((e = k::bpupdate(s, n, dinv, R64, P32, vblocks, sc, nullptr)) != hipSuccess) return e;
     }
     return hipSuccess;
   };
@@ -239,14 +237,11 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
     for (int col = 0; col < 64; ++col) {
       const int d = hs->done[col];
       flagged[col] = (d >= 1 && d <= 4) ? d : 0;
-      if (flagged[col]) {
-        hp.action[col] = 1;
-        hp.scale[col] = scale[col];
-      }
+      hp.action[col] = flagged[col] ? 1 : 0;
     }
     FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
-    FEMH_TRY_HIP(k::bfold(s, n, X32, X64, vblocks, plan));
-    FEMH_TRY_HIP(k::bresidual64(s, P->pat, P->val64, X64, B64, R64, (double*)partials, rblocks, 64, rr64));
+    // true residual into the flagged columns only
+    FEMH_TRY_HIP(k::bresidual64(s, P->pat, P->val64, X64, B64, R64, partials, rblocks, 64, rr64, plan->action));
     FEMH_TRY_HIP(hipMemcpyAsync(hrr.data(), rr64, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
     FEMH_TRY_HIP(hipStreamSynchronize(s));
     std::memset(&hp, 0, sizeof(hp));
@@ -265,17 +260,13 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
         hp.final_state[col] = 6;
         final_status[col] = FEMH_E_NOT_CONVERGED;
       } else {
-        const double ns = std::sqrt(hrr[col]);
         hp.action[col] = flagged[col] == 3 ? 2 : 1;
-        hp.inv_s[col] = 1.0 / ns;
-        hp.ratio[col] = scale[col] / ns;
-        hp.tol2[col] = o.rtol * o.rtol * bb[col] / (ns * ns);
-        scale[col] = ns;
+        hp.tol2[col] = o.rtol * o.rtol * bb[col];
       }
     }
     FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
-    FEMH_TRY_HIP(k::brescale(s, n, R64, dinv, R32, P32, partials, vblocks, 64, sc, plan));
-    FEMH_TRY_HIP(k::bpupdate(s, n, dinv, R32, P32, vblocks, sc, plan->action));
+    FEMH_TRY_HIP(k::brescale(s, n, R64, dinv, P32, partials, vblocks, 64, sc, plan));
+    FEMH_TRY_HIP(k::bpupdate(s, n, dinv, R64, P32, vblocks, sc, plan->action));
     FEMH_TRY_HIP(run_chunk());
   }
   FEMH_TRY_HIP(hipStreamSynchronize(s));

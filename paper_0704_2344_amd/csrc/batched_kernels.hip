@@ -1,23 +1,29 @@
 // Batched right-hand sides: the block-sparse matrix times a dense block of up
-// to 64 complex64 columns (SpMM), and per-column COCG steps.
+// to 64 columns (SpMM), and per-column COCG steps.  Each column keeps its
+// iterate and residual recurrence in FP64; only the directions P are stored
+// in complex64.  The product Q = A P is formed in FP64 arithmetic and kept
+// in FP64: summing a row's 81 complex terms in FP32 perturbs the product by
+// enough to destroy the conjugacy of the directions on large indefinite
+// systems (the columns then stagnate), while rounding only the directions
+// to complex64 costs a few percent of iterations.
 //
-// Layout: a block vector is [n_unknowns][64] complex64 (column fastest), so
-// the 64 columns of one unknown are 512 contiguous bytes and a wavefront
-// with lane = column reads them in one coalesced access.
+// Layout: a block vector is [n_unknowns][64] (column fastest), so the 64
+// columns of one unknown are contiguous and a wavefront with lane = column
+// reads them in one coalesced access.
 //
-// SpMM on the matrix cores.  For one block row r the product is a dense
-// (3 x 3 nb) x (3 nb x 64) complex contraction.  v_mfma_f32_4x4x1_16b_f32
-// computes 16 independent 4x4x1 outer products: lane l supplies A of block
-// l/4 row l%4 and B of block l/4 column l%4, and lane l receives C of block
-// l/4 column l%4 in its four accumulator registers (rows 0..3).  With the
-// block index = column group, lane l therefore owns RHS column l, and the
-// accumulator registers hold the three row components (the fourth row is
-// zero padding).  Each complex multiply-add uses three real products
-// (Re = k1 - k2, Im = k1 + k3 with k1 = Ar (Xr + Xi), k2 = Xi (Ar + Ai),
-// k3 = Xr (Ai - Ar)), i.e. three MFMAs per (block, column component).
-//
-// A vector-FMA SpMM with the same layout (lane = column, several rows per
-// wave for narrow blocks) is the alternative the autotuner compares against.
+// Two SpMM kernels, chosen by timing:
+//  * vector FMAs: the complex128 matrix times the promoted complex64
+//    directions, FP64 FMAs, lane = column;
+//  * matrix cores: v_mfma_f32_4x4x1_16b_f32 computes 16 independent 4x4x1
+//    outer products: lane l supplies A of block l/4 row l%4 and B of block
+//    l/4 column l%4, and receives C of block l/4 column l%4 in its four
+//    accumulator registers (rows 0..3).  With the block index = column
+//    group, lane l owns RHS column l and the registers hold the three row
+//    components (row 3 is padding).  Each complex 3x3 block times the
+//    column's three components takes four MFMAs per component (Ar Xr, Ai Xi,
+//    Ar Xi, Ai Xr) on the complex64 matrix in FP32; the block's result is
+//    then added into FP64 row accumulators, so FP32 rounding never sees
+//    more than one block's three terms.
 //
 // Per-column dot products are written as per-workgroup partials and summed
 // in a fixed order by a separate per-column reduction kernel.
@@ -61,9 +67,18 @@ __device__ __forceinline__ void store_col_partials(const double (&v)[4], double*
   }
 }
 
-// Q = A P on the matrix cores, with per-column p^T q.
+// Per-column p^T q, ||p||^2, ||q||^2 of one row component.
+__device__ __forceinline__ void pq_terms(const float2 p, double yr, double yi, double (&acc)[4]) {
+  acc[0] += (double)p.x * yr - (double)p.y * yi;
+  acc[1] += (double)p.x * yi + (double)p.y * yr;
+  acc[2] += (double)p.x * p.x + (double)p.y * p.y;
+  acc[3] += yr * yr + yi * yi;
+}
+
+// Q = A P on the matrix cores (complex64 matrix, FP32 products per block,
+// FP64 sum over blocks), with per-column p^T q.
 __global__ void __launch_bounds__(kBT) k_bspmm_mfma(PatternDev pt, const float2* __restrict__ val,
-                                                    const float2* __restrict__ P, float2* __restrict__ Q,
+                                                    const float2* __restrict__ P, double2* __restrict__ Q,
                                                     double* __restrict__ partials, const BatchScalars* sc) {
   if (sc->active == 0) return;
   const int lane = threadIdx.x & 63;
@@ -73,40 +88,41 @@ __global__ void __launch_bounds__(kBT) k_bspmm_mfma(PatternDev pt, const float2*
   for (int r = wave_index(kBT / 64, nwaves); r < pt.nn; r += nwaves) {
     const int beg = uniform_int(pt.row_ptr[r]);
     const int end = uniform_int(pt.row_ptr[r + 1]);
-    v4f K1 = {0.f, 0.f, 0.f, 0.f}, K2 = K1, K3 = K1;
+    double yr[3] = {0.0, 0.0, 0.0}, yi[3] = {0.0, 0.0, 0.0};
     for (int b = beg; b < end; ++b) {
       const int c = uniform_int(pt.col_idx[b]);
       const float2* blk = val + (size_t)b * 9;
       const float2* xrow = P + (size_t)3 * c * kLD + lane;
+      v4f K1 = {0.f, 0.f, 0.f, 0.f}, K2 = K1, K3 = K1, K4 = K1;
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        float2 a = m < 3 ? blk[3 * m + j] : make_float2(0.f, 0.f);
+        const float2 a = m < 3 ? blk[3 * m + j] : make_float2(0.f, 0.f);
         const float2 x = xrow[j * kLD];
-        const float a1 = a.x, a2 = a.x + a.y, a3 = a.y - a.x;
-        K1 = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, x.x + x.y, K1, 0, 0, 0);
-        K2 = __builtin_amdgcn_mfma_f32_4x4x1f32(a2, x.y, K2, 0, 0, 0);
-        K3 = __builtin_amdgcn_mfma_f32_4x4x1f32(a3, x.x, K3, 0, 0, 0);
+        K1 = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, x.x, K1, 0, 0, 0);
+        K2 = __builtin_amdgcn_mfma_f32_4x4x1f32(a.y, x.y, K2, 0, 0, 0);
+        K3 = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, x.y, K3, 0, 0, 0);
+        K4 = __builtin_amdgcn_mfma_f32_4x4x1f32(a.y, x.x, K4, 0, 0, 0);
+      }
+      // lane = column; register i = row component
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        yr[i] += (double)K1[i] - (double)K2[i];
+        yi[i] += (double)K3[i] + (double)K4[i];
       }
     }
-    // lane = column; register i = row component
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const float yr = K1[i] - K2[i], yi = K1[i] + K3[i];
       const size_t idx = (size_t)(3 * r + i) * kLD + lane;
-      Q[idx] = make_float2(yr, yi);
-      const float2 p = P[idx];
-      acc[0] += (double)p.x * yr - (double)p.y * yi;
-      acc[1] += (double)p.x * yi + (double)p.y * yr;
-      acc[2] += (double)p.x * p.x + (double)p.y * p.y;
-      acc[3] += (double)yr * yr + (double)yi * yi;
+      Q[idx] = make_double2(yr[i], yi[i]);
+      pq_terms(P[idx], yr[i], yi[i], acc);
     }
   }
   store_col_partials(acc, partials);
 }
 
-// Same product with vector FMAs (lane = column).
-__global__ void __launch_bounds__(kBT) k_bspmm_vec(PatternDev pt, const float2* __restrict__ val,
-                                                   const float2* __restrict__ P, float2* __restrict__ Q,
+// Same product with FP64 vector FMAs on the complex128 matrix (lane = column).
+__global__ void __launch_bounds__(kBT) k_bspmm_vec(PatternDev pt, const double2* __restrict__ val,
+                                                   const float2* __restrict__ P, double2* __restrict__ Q,
                                                    double* __restrict__ partials, const BatchScalars* sc) {
   if (sc->active == 0) return;
   const int lane = threadIdx.x & 63;
@@ -115,15 +131,16 @@ __global__ void __launch_bounds__(kBT) k_bspmm_vec(PatternDev pt, const float2* 
   for (int r = wave_index(kBT / 64, nwaves); r < pt.nn; r += nwaves) {
     const int beg = uniform_int(pt.row_ptr[r]);
     const int end = uniform_int(pt.row_ptr[r + 1]);
-    float yr[3] = {0.f, 0.f, 0.f}, yi[3] = {0.f, 0.f, 0.f};
+    double yr[3] = {0.0, 0.0, 0.0}, yi[3] = {0.0, 0.0, 0.0};
     for (int b = beg; b < end; ++b) {
       const int c = uniform_int(pt.col_idx[b]);
-      const float2* blk = val + (size_t)b * 9;
+      const double2* blk = val + (size_t)b * 9;
       const float2* xrow = P + (size_t)3 * c * kLD + lane;
-      const float2 x0 = xrow[0], x1 = xrow[kLD], x2 = xrow[2 * kLD];
+      const float2 f0 = xrow[0], f1 = xrow[kLD], f2 = xrow[2 * kLD];
+      const double2 x0 = make_double2(f0.x, f0.y), x1 = make_double2(f1.x, f1.y), x2 = make_double2(f2.x, f2.y);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const float2 a0 = blk[3 * i], a1 = blk[3 * i + 1], a2 = blk[3 * i + 2];
+        const double2 a0 = blk[3 * i], a1 = blk[3 * i + 1], a2 = blk[3 * i + 2];
         yr[i] += a0.x * x0.x - a0.y * x0.y + a1.x * x1.x - a1.y * x1.y + a2.x * x2.x - a2.y * x2.y;
         yi[i] += a0.x * x0.y + a0.y * x0.x + a1.x * x1.y + a1.y * x1.x + a2.x * x2.y + a2.y * x2.x;
       }
@@ -131,12 +148,8 @@ __global__ void __launch_bounds__(kBT) k_bspmm_vec(PatternDev pt, const float2* 
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const size_t idx = (size_t)(3 * r + i) * kLD + lane;
-      Q[idx] = make_float2(yr[i], yi[i]);
-      const float2 p = P[idx];
-      acc[0] += (double)p.x * yr[i] - (double)p.y * yi[i];
-      acc[1] += (double)p.x * yi[i] + (double)p.y * yr[i];
-      acc[2] += (double)p.x * p.x + (double)p.y * p.y;
-      acc[3] += (double)yr[i] * yr[i] + (double)yi[i] * yi[i];
+      Q[idx] = make_double2(yr[i], yi[i]);
+      pq_terms(P[idx], yr[i], yi[i], acc);
     }
   }
   store_col_partials(acc, partials);
@@ -235,67 +248,75 @@ __global__ void __launch_bounds__(kBT) k_bred_beta(const double* __restrict__ pa
   }
 }
 
-// x += alpha p; r -= alpha q; z = D^-1 r; per-column rho', ||r||^2, ||z||^2.
-__global__ void __launch_bounds__(kBT) k_bupdate(int64_t n, const float2* __restrict__ dinv, float2* __restrict__ X,
-                                                 float2* __restrict__ R, const float2* __restrict__ P,
-                                                 const float2* __restrict__ Q, double* __restrict__ partials,
+// x += alpha p; r -= alpha q (FP64); z = D^-1 r; per-column rho', ||r||^2,
+// ||z||^2.
+__global__ void __launch_bounds__(kBT) k_bupdate(int64_t n, const double2* __restrict__ dinv, double2* __restrict__ X,
+                                                 double2* __restrict__ R, const float2* __restrict__ P,
+                                                 const double2* __restrict__ Q, double* __restrict__ partials,
                                                  const BatchScalars* sc) {
   if (sc->active == 0) return;
   const int col = threadIdx.x & 63;
   const bool on = sc->done[col] == 0;
-  const float ar = (float)sc->alpha[col].x, ai = (float)sc->alpha[col].y;
+  const double ar = sc->alpha[col].x, ai = sc->alpha[col].y;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t rows_per_block = kBT / 64;
   for (int64_t u = (int64_t)blockIdx.x * rows_per_block + (threadIdx.x >> 6); u < n;
        u += (int64_t)gridDim.x * rows_per_block) {
     if (!on) continue;
     const size_t idx = (size_t)u * kLD + col;
-    const float2 p = P[idx], q = Q[idx], d = dinv[u];
-    float2 x = X[idx], r = R[idx];
-    x.x += ar * p.x - ai * p.y;
-    x.y += ar * p.y + ai * p.x;
+    const float2 p = P[idx];
+    const double2 q = Q[idx];
+    const double2 d = dinv[u];
+    double2 x = X[idx];
+    double2 r = R[idx];
+    x.x += ar * (double)p.x - ai * (double)p.y;
+    x.y += ar * (double)p.y + ai * (double)p.x;
     r.x -= ar * q.x - ai * q.y;
     r.y -= ar * q.y + ai * q.x;
     X[idx] = x;
     R[idx] = r;
-    const float zr = d.x * r.x - d.y * r.y, zi = d.x * r.y + d.y * r.x;
-    v[0] += (double)r.x * zr - (double)r.y * zi;
-    v[1] += (double)r.x * zi + (double)r.y * zr;
-    v[2] += (double)r.x * r.x + (double)r.y * r.y;
-    v[3] += (double)zr * zr + (double)zi * zi;
+    const double zr = d.x * r.x - d.y * r.y, zi = d.x * r.y + d.y * r.x;
+    v[0] += r.x * zr - r.y * zi;
+    v[1] += r.x * zi + r.y * zr;
+    v[2] += r.x * r.x + r.y * r.y;
+    v[3] += zr * zr + zi * zi;
   }
   store_col_partials(v, partials);
 }
 
-// p = D^-1 r + beta p for running columns (also used right after a
-// reliable update, for the columns that keep their direction).
-__global__ void __launch_bounds__(kBT) k_bpupdate(int64_t n, const float2* __restrict__ dinv,
-                                                  const float2* __restrict__ R, float2* __restrict__ P,
+// p = D^-1 r + beta p (direction kept in complex64) for running columns,
+// or for the columns with only[c] == 1 right after a reliable update.
+__global__ void __launch_bounds__(kBT) k_bpupdate(int64_t n, const double2* __restrict__ dinv,
+                                                  const double2* __restrict__ R, float2* __restrict__ P,
                                                   const BatchScalars* sc, const int32_t* __restrict__ only) {
   if (sc->active == 0 && !only) return;
   const int col = threadIdx.x & 63;
   const bool on = only ? only[col] == 1 : sc->done[col] == 0;
   if (!on) return;
-  const float br = (float)sc->beta[col].x, bi = (float)sc->beta[col].y;
+  const double br = sc->beta[col].x, bi = sc->beta[col].y;
   const int64_t rows_per_block = kBT / 64;
   for (int64_t u = (int64_t)blockIdx.x * rows_per_block + (threadIdx.x >> 6); u < n;
        u += (int64_t)gridDim.x * rows_per_block) {
     const size_t idx = (size_t)u * kLD + col;
-    const float2 d = dinv[u], r = R[idx];
-    float2 p = P[idx];
-    const float zr = d.x * r.x - d.y * r.y, zi = d.x * r.y + d.y * r.x;
-    const float nr = zr + br * p.x - bi * p.y;
-    const float ni = zi + br * p.y + bi * p.x;
-    P[idx] = make_float2(nr, ni);
+    const double2 d = dinv[u], r = R[idx];
+    const float2 p = P[idx];
+    const double zr = d.x * r.x - d.y * r.y, zi = d.x * r.y + d.y * r.x;
+    const double nr = zr + br * p.x - bi * p.y;
+    const double ni = zi + br * p.y + bi * p.x;
+    P[idx] = make_float2((float)nr, (float)ni);
   }
 }
 
 // ------------------------------------------------------------ FP64 parts
 // R = B - A X in FP64 (vector FMAs, lane = column) with per-column ||R||^2.
+// R = B - A X in FP64 for the columns with mask[c] != 0 (all when mask is
+// null); per-column ||B - A X||^2 for every column.
 __global__ void __launch_bounds__(kBT) k_bresidual64(PatternDev pt, const double2* __restrict__ val,
                                                      const double2* __restrict__ X, const double2* __restrict__ B,
-                                                     double2* __restrict__ R, double* __restrict__ partials) {
+                                                     double2* __restrict__ R, double* __restrict__ partials,
+                                                     const int32_t* __restrict__ mask) {
   const int lane = threadIdx.x & 63;
+  const bool store = mask ? mask[lane] != 0 : true;
   double acc = 0.0;
   int nwaves;
   for (int r = wave_index(kBT / 64, nwaves); r < pt.nn; r += nwaves) {
@@ -319,7 +340,7 @@ __global__ void __launch_bounds__(kBT) k_bresidual64(PatternDev pt, const double
       const size_t idx = (size_t)(3 * r + i) * kLD + lane;
       const double2 b = B[idx];
       const double2 rv = make_double2(b.x - yr[i], b.y - yi[i]);
-      R[idx] = rv;
+      if (store) R[idx] = rv;
       acc += rv.x * rv.x + rv.y * rv.y;
     }
   }
@@ -348,52 +369,29 @@ __global__ void __launch_bounds__(kBT) k_bred_norm64(const double* __restrict__ 
   if (threadIdx.x == 0) rr64[col] = s[0];
 }
 
-// Fold the complex64 partial solution of flagged columns into X64 and
-// clear it: X64 += scale_c X32.
-__global__ void __launch_bounds__(kBT) k_bfold(int64_t n, float2* __restrict__ X32, double2* __restrict__ X64,
-                                               const BatchPlan* __restrict__ plan) {
-  const int col = threadIdx.x & 63;
-  if (plan->action[col] == 0) return;
-  const double s = plan->scale[col];
-  const int64_t rows_per_block = kBT / 64;
-  for (int64_t u = (int64_t)blockIdx.x * rows_per_block + (threadIdx.x >> 6); u < n;
-       u += (int64_t)gridDim.x * rows_per_block) {
-    const size_t idx = (size_t)u * kLD + col;
-    const float2 d = X32[idx];
-    double2 x = X64[idx];
-    x.x += s * (double)d.x;
-    x.y += s * (double)d.y;
-    X64[idx] = x;
-    X32[idx] = make_float2(0.f, 0.f);
-  }
-}
-
-// Reliable update of flagged columns: R32 = R64 / s_new; z = D^-1 R32;
-// fresh columns restart p = z.  Per-column rho', ||r||^2, ||z||^2 partials.
-__global__ void __launch_bounds__(kBT) k_brescale(int64_t n, const double2* __restrict__ R64,
-                                                  const float2* __restrict__ dinv, float2* __restrict__ R32,
-                                                  float2* __restrict__ P, double* __restrict__ partials,
-                                                  const BatchPlan* __restrict__ plan) {
+// Reliable update of flagged columns whose residual was just replaced by
+// the true one: rho' = r^T D^-1 r; restarting columns (action 2) take
+// p = D^-1 r.  Per-column rho', ||r||^2, ||z||^2 partials.
+__global__ void __launch_bounds__(kBT) k_brescale(int64_t n, const double2* __restrict__ R,
+                                                  const double2* __restrict__ dinv, float2* __restrict__ P,
+                                                  double* __restrict__ partials, const BatchPlan* __restrict__ plan) {
   const int col = threadIdx.x & 63;
   const int act = plan->action[col];
   const bool on = act == 1 || act == 2;
-  const double inv_s = plan->inv_s[col];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t rows_per_block = kBT / 64;
   if (on) {
     for (int64_t u = (int64_t)blockIdx.x * rows_per_block + (threadIdx.x >> 6); u < n;
          u += (int64_t)gridDim.x * rows_per_block) {
       const size_t idx = (size_t)u * kLD + col;
-      const double2 s = R64[idx];
-      const float2 r = make_float2((float)(s.x * inv_s), (float)(s.y * inv_s));
-      const float2 d = dinv[u];
-      const float zr = d.x * r.x - d.y * r.y, zi = d.x * r.y + d.y * r.x;
-      R32[idx] = r;
-      if (act == 2) P[idx] = make_float2(zr, zi);
-      v[0] += (double)r.x * zr - (double)r.y * zi;
-      v[1] += (double)r.x * zi + (double)r.y * zr;
-      v[2] += (double)r.x * r.x + (double)r.y * r.y;
-      v[3] += (double)zr * zr + (double)zi * zi;
+      const double2 r = R[idx];
+      const double2 d = dinv[u];
+      const double zr = d.x * r.x - d.y * r.y, zi = d.x * r.y + d.y * r.x;
+      if (act == 2) P[idx] = make_float2((float)zr, (float)zi);
+      v[0] += r.x * zr - r.y * zi;
+      v[1] += r.x * zi + r.y * zr;
+      v[2] += r.x * r.x + r.y * r.y;
+      v[3] += zr * zr + zi * zi;
     }
   }
   store_col_partials(v, partials);
@@ -419,8 +417,7 @@ __global__ void __launch_bounds__(kBT) k_bred_rescale(const double* __restrict__
     if (cabs2(rho_new) <= sc->bd_tol * sc->bd_tol * rr * zz) {
       sc->done[col] = 3;
     } else if (act == 1) {
-      const double ratio = plan->ratio[col];
-      sc->beta[col] = cdiv(rho_new, make_double2(sc->rho[col].x * ratio, sc->rho[col].y * ratio));
+      sc->beta[col] = cdiv(rho_new, sc->rho[col]);
     }
     sc->rho[col] = rho_new;
   }
@@ -472,12 +469,12 @@ int batched_vec_blocks(int64_t n) {
   return (int)b;
 }
 
-hipError_t bspmm(hipStream_t st, const PatternDev& pt, const float2* val, const float2* P, float2* Q,
-                 double* partials, const BatchScalars* sc, BatchTile tile) {
+hipError_t bspmm(hipStream_t st, const PatternDev& pt, const double2* val64, const float2* val32, const float2* P,
+                 double2* Q, double* partials, const BatchScalars* sc, BatchTile tile) {
   if (tile.kind == 1)
-    hipLaunchKernelGGL(k_bspmm_mfma, dim3(tile.blocks), dim3(kBT), 0, st, pt, val, P, Q, partials, sc);
+    hipLaunchKernelGGL(k_bspmm_mfma, dim3(tile.blocks), dim3(kBT), 0, st, pt, val32, P, Q, partials, sc);
   else
-    hipLaunchKernelGGL(k_bspmm_vec, dim3(tile.blocks), dim3(kBT), 0, st, pt, val, P, Q, partials, sc);
+    hipLaunchKernelGGL(k_bspmm_vec, dim3(tile.blocks), dim3(kBT), 0, st, pt, val64, P, Q, partials, sc);
   return hipGetLastError();
 }
 
@@ -486,8 +483,8 @@ hipError_t bred_alpha(hipStream_t st, const double* partials, int nblocks, int n
   return hipGetLastError();
 }
 
-hipError_t bupdate(hipStream_t st, int64_t n, const float2* dinv, float2* X, float2* R, const float2* P,
-                   const float2* Q, double* partials, int blocks, const BatchScalars* sc) {
+hipError_t bupdate(hipStream_t st, int64_t n, const double2* dinv, double2* X, double2* R, const float2* P,
+                   const double2* Q, double* partials, int blocks, const BatchScalars* sc) {
   hipLaunchKernelGGL(k_bupdate, dim3(blocks), dim3(kBT), 0, st, n, dinv, X, R, P, Q, partials, sc);
   return hipGetLastError();
 }
@@ -497,27 +494,23 @@ hipError_t bred_beta(hipStream_t st, const double* partials, int nblocks, int nc
   return hipGetLastError();
 }
 
-hipError_t bpupdate(hipStream_t st, int64_t n, const float2* dinv, const float2* R, float2* P, int blocks,
+hipError_t bpupdate(hipStream_t st, int64_t n, const double2* dinv, const double2* R, float2* P, int blocks,
                     const BatchScalars* sc, const int32_t* only) {
   hipLaunchKernelGGL(k_bpupdate, dim3(blocks), dim3(kBT), 0, st, n, dinv, R, P, sc, only);
   return hipGetLastError();
 }
 
 hipError_t bresidual64(hipStream_t st, const PatternDev& pt, const double2* val, const double2* X,
-                       const double2* B, double2* R, double* partials, int blocks, int ncols, double* rr64) {
-  hipLaunchKernelGGL(k_bresidual64, dim3(blocks), dim3(kBT), 0, st, pt, val, X, B, R, partials);
+                       const double2* B, double2* R, double* partials, int blocks, int ncols, double* rr64,
+                       const int32_t* mask) {
+  hipLaunchKernelGGL(k_bresidual64, dim3(blocks), dim3(kBT), 0, st, pt, val, X, B, R, partials, mask);
   hipLaunchKernelGGL(k_bred_norm64, dim3(ncols), dim3(kBT), 0, st, (const double*)partials, blocks, rr64);
   return hipGetLastError();
 }
 
-hipError_t bfold(hipStream_t st, int64_t n, float2* X32, double2* X64, int blocks, const BatchPlan* plan) {
-  hipLaunchKernelGGL(k_bfold, dim3(blocks), dim3(kBT), 0, st, n, X32, X64, plan);
-  return hipGetLastError();
-}
-
-hipError_t brescale(hipStream_t st, int64_t n, const double2* R64, const float2* dinv, float2* R32, float2* P,
+hipError_t brescale(hipStream_t st, int64_t n, const double2* R, const double2* dinv, float2* P,
                     double* partials, int blocks, int ncols, BatchScalars* sc, const BatchPlan* plan) {
-  hipLaunchKernelGGL(k_brescale, dim3(blocks), dim3(kBT), 0, st, n, R64, dinv, R32, P, partials, plan);
+  hipLaunchKernelGGL(k_brescale, dim3(blocks), dim3(kBT), 0, st, n, R, dinv, P, partials, plan);
   hipLaunchKernelGGL(k_bred_rescale, dim3(ncols), dim3(kBT), 0, st, (const double*)partials, blocks, sc, plan);
   hipLaunchKernelGGL(k_bcount_active, dim3(1), dim3(64), 0, st, sc, ncols);
   return hipGetLastError();

@@ -265,7 +265,12 @@ int femh_solve_batched_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wa
     femh::set_error("%s", m.c_str());
     return st;
   }
-  const femh_solve_opts o = femh::opts_with_defaults(opts);
+  // the batched recurrence is the matrix-mixed one (FP64 residuals,
+  // complex64 SpMM operands) whatever opts->precision says
+  femh_solve_opts ob{};
+  if (opts) ob = *opts;
+  ob.precision = FEMH_MIXED_MATRIX;
+  const femh_solve_opts o = femh::opts_with_defaults(&ob);
   if (o.precond != FEMH_PRECOND_JACOBI && o.precond != FEMH_PRECOND_NONE) {
     femh::set_error("unknown preconditioner %d", o.precond);
     return FEMH_E_INVALID;
@@ -298,20 +303,20 @@ int femh_spmm_dev(femh_problem* p, int32_t ncols, const void* X, void* Y, int32_
   hipStream_t s = c->stream;
   const int64_t n = 3 * (int64_t)p->pat.nn;
   const bool direct = ncols == 64;
-  DevTmp xp(c, direct ? 16 : 8 * (size_t)n * 64), yp(c, direct ? 16 : 8 * (size_t)n * 64);
+  DevTmp xp(c, direct ? 16 : 8 * (size_t)n * 64), yp(c, direct ? 16 : 16 * (size_t)n * 64);
   DevTmp part(c, 2048 * 64 * 4 * sizeof(double)), scd(c, sizeof(femh::BatchScalars));
   if (!xp.p || !yp.p || !part.p || !scd.p) {
     femh::set_error("device allocation failed (spmm)");
     return FEMH_E_OOM;
   }
   const float2* Xd = (const float2*)X;
-  float2* Yd = (float2*)Y;
+  double2* Yd = (double2*)Y;
   if (!direct) {
     FEMH_TRY_HIP(hipMemsetAsync(xp.p, 0, 8 * (size_t)n * 64, s));
     FEMH_TRY_HIP(hipMemcpy2DAsync(xp.p, 64 * 8, X, (size_t)ncols * 8, (size_t)ncols * 8, (size_t)n,
                                   hipMemcpyDeviceToDevice, s));
     Xd = (const float2*)xp.p;
-    Yd = (float2*)yp.p;
+    Yd = (double2*)yp.p;
   }
   femh::BatchScalars* hs = reinterpret_cast<femh::BatchScalars*>(c->pinned);
   std::memset(hs, 0, sizeof(*hs));
@@ -324,7 +329,7 @@ int femh_spmm_dev(femh_problem* p, int32_t ncols, const void* X, void* Y, int32_
   FEMH_TRY_HIP(hipEventCreate(&e1));
   FEMH_TRY_HIP(hipEventRecord(e0, s));
   for (int i = 0; i < reps; ++i)
-    FEMH_TRY_HIP(femh::k::bspmm(s, p->pat, p->val32, Xd, Yd, (double*)part.p, (const femh::BatchScalars*)scd.p,
+    FEMH_TRY_HIP(femh::k::bspmm(s, p->pat, p->val64, p->val32, Xd, Yd, (double*)part.p, (const femh::BatchScalars*)scd.p,
                                 p->tile));
   FEMH_TRY_HIP(hipEventRecord(e1, s));
   FEMH_TRY_HIP(hipEventSynchronize(e1));
@@ -334,7 +339,7 @@ int femh_spmm_dev(femh_problem* p, int32_t ncols, const void* X, void* Y, int32_
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (!direct)
-    FEMH_TRY_HIP(hipMemcpy2DAsync(Y, (size_t)ncols * 8, yp.p, 64 * 8, (size_t)ncols * 8, (size_t)n,
+    FEMH_TRY_HIP(hipMemcpy2DAsync(Y, (size_t)ncols * 16, yp.p, 64 * 16, (size_t)ncols * 16, (size_t)n,
                                   hipMemcpyDeviceToDevice, s));
   FEMH_TRY_HIP(hipStreamSynchronize(s));
   return FEMH_OK;

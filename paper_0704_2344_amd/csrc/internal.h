@@ -100,16 +100,13 @@ struct BatchScalars {
   double bd_tol;
 };
 
-// Host-written plan of one reliable update.  action[c]: 0 none, 1 fold +
-// rescale keeping the direction, 2 fold + rescale restarting the direction,
-// 3 fold and finish with final_state[c].
+// Host-written plan of one reliable update.  action[c]: 0 none, 1 replace
+// the residual and keep the direction, 2 replace the residual and restart
+// the direction, 3 finish with final_state[c].
 struct BatchPlan {
   int32_t action[64];
   int32_t final_state[64];
-  double scale[64];   // fold: X64 += scale * X32
-  double inv_s[64];   // rescale: R32 = R64 * inv_s
-  double ratio[64];   // s_old / s_new
-  double tol2[64];    // recursive tolerance in the new scaling
+  double tol2[64];    // recursive tolerance (absolute ||r||^2)
 };
 
 // SpMM tile choice: kind 1 = matrix cores, 0 = vector FMAs; blocks = grid.
@@ -125,18 +122,19 @@ namespace k {
 int batched_blocks_for(int32_t nn, int n_cu, int per_cu);
 int batched_vec_blocks(int64_t n);
 // per-column partial sums are FP64: partials hold [blocks][64][4] doubles
-hipError_t bspmm(hipStream_t st, const PatternDev& pt, const float2* val, const float2* P, float2* Q,
-                 double* partials, const BatchScalars* sc, BatchTile tile);
+// kind 0 reads the complex128 matrix, kind 1 the complex64 one; Q is FP64
+hipError_t bspmm(hipStream_t st, const PatternDev& pt, const double2* val64, const float2* val32, const float2* P,
+                 double2* Q, double* partials, const BatchScalars* sc, BatchTile tile);
 hipError_t bred_alpha(hipStream_t st, const double* partials, int nblocks, int ncols, BatchScalars* sc);
-hipError_t bupdate(hipStream_t st, int64_t n, const float2* dinv, float2* X, float2* R, const float2* P,
-                   const float2* Q, double* partials, int blocks, const BatchScalars* sc);
+hipError_t bupdate(hipStream_t st, int64_t n, const double2* dinv, double2* X, double2* R, const float2* P,
+                   const double2* Q, double* partials, int blocks, const BatchScalars* sc);
 hipError_t bred_beta(hipStream_t st, const double* partials, int nblocks, int ncols, BatchScalars* sc);
-hipError_t bpupdate(hipStream_t st, int64_t n, const float2* dinv, const float2* R, float2* P, int blocks,
+hipError_t bpupdate(hipStream_t st, int64_t n, const double2* dinv, const double2* R, float2* P, int blocks,
                     const BatchScalars* sc, const int32_t* only);
 hipError_t bresidual64(hipStream_t st, const PatternDev& pt, const double2* val, const double2* X,
-                       const double2* B, double2* R, double* partials, int blocks, int ncols, double* rr64);
-hipError_t bfold(hipStream_t st, int64_t n, float2* X32, double2* X64, int blocks, const BatchPlan* plan);
-hipError_t brescale(hipStream_t st, int64_t n, const double2* R64, const float2* dinv, float2* R32, float2* P,
+                       const double2* B, double2* R, double* partials, int blocks, int ncols, double* rr64,
+                       const int32_t* mask);
+hipError_t brescale(hipStream_t st, int64_t n, const double2* R, const double2* dinv, float2* P,
                     double* partials, int blocks, int ncols, BatchScalars* sc, const BatchPlan* plan);
 hipError_t to_block(hipStream_t st, int64_t n, int nrhs, const double2* b, double2* B);
 hipError_t from_block(hipStream_t st, int64_t n, int nrhs, const double2* X, double2* x);
@@ -309,7 +307,7 @@ int solve_single(Problem* P, const double2* b, double2* x, const femh_solve_opts
 int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh_solve_opts& o,
                   femh_solve_stats* st);
 // Pick the SpMM tile for a problem (timed candidates), cached on the problem.
-int autotune_spmm(Problem* P, const float2* Pv, float2* Qv, double* partials, const BatchScalars* sc);
+int autotune_spmm(Problem* P, const float2* Pv, double2* Qv, double* partials, const BatchScalars* sc);
 
 // Single-RHS solve as a non-blocking state machine (one code path for
 // femh_solve and the server).  step() queues the work its phase allows and
