@@ -255,8 +255,10 @@ def test_sphere_shell_60_bench_configuration(ctx, torch):
     """The benchmarked workload (60^3, PEC sphere + dielectric shell, 644 136
     unknowns) in the benchmark's launch configuration: sampled block rows
     against the oracle's one-row assembly, sampled SpMV rows in both
-    precisions, and the mixed solve's backward error to 1e-6 under the
-    oracle's full matrix."""
+    precisions, and the complex64-matrix solve's backward error to 1e-6
+    under the oracle's full matrix.  The lossless dielectric coating makes
+    this system hard for Jacobi-COCG (about 48 000 iterations); the
+    complex64-vector mode breaks down on it and is not used here."""
     prob, waves = W.pec_sphere_shell(60)
     P = F.Problem(ctx, prob)
     assert P.n_unknowns == 644136 and P.nnzb == 5561948
@@ -300,9 +302,9 @@ def test_sphere_shell_60_bench_configuration(ctx, torch):
             bnd32 += abs(b32) @ abs(x32[3 * c:3 * c + 3])
         assert np.all(abs(y[3 * a:3 * a + 3] - yo) <= 1e-13 * bnd)
         assert np.all(abs(y32[3 * a:3 * a + 3] - yo32) <= 2e-6 * bnd32)
-    # mixed-precision solve to an FP64 residual of 1e-6
+    # complex64-matrix solve to an FP64 residual of 1e-6
     out = torch.zeros(P.grid_shape(1), dtype=torch.complex128, device="cuda")
-    stats, st = P.solve_dev(waves, out, precision=F.FEMH_MIXED, rtol=1e-6)
+    stats, st = P.solve_dev(waves, out, precision=F.FEMH_MIXED_MATRIX, rtol=1e-6, max_iter=100000)
     assert st == F.FEMH_OK, stats
     Ao = fem.assemble(prob)
     b = fem.rhs(prob, waves)[:, 0]
