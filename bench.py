@@ -17,7 +17,13 @@ Also printed on the same JSON line:
                 shell matrix (845 MB complex128, 434 MB complex64: larger
                 than the 256 MB Infinity Cache)
   batched       the 40^3 PEC-sphere workload with 64 right-hand sides as one
-                batched complex64 solve to 1e-6 (RHS/s)
+                batched solve to 1e-6 (RHS/s, SpMM time, GB/s and TFLOP/s),
+                against single-RHS matrix-mixed solves of the same waves
+  serving       a Poisson stream of scattering requests (meshes n^3 with n in
+                [10, serve_n_hi], 1-4 waves each) through the continuous-
+                batching server in matrix-mixed and FP64 precision, and the
+                plain FP64 solver one request at a time, all to 1e-6:
+                requests/s, RHS/s, p50/p99 latency from arrival
   roofline      the dominant kernel of the timed steps (the FP64 block SpMV
                 fused with p^T A p), timed with HIP events around every
                 launch in the timed region
@@ -36,12 +42,106 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E datasheet
 
+# HBM traffic of the dominant kernel from two rocprofv3 counter runs
+# (FETCH_SIZE, then WRITE_SIZE; mean KiB per working dispatch of the FP64
+# SpMV-dot on the headline workload), each scaled by what the same counter
+# reads for the 1 GiB copy probe (1 GiB read + 1 GiB written) in the same
+# run.  Valid only for the kernel source it was taken on: reported as null
+# once that file changes.
+MEASURED_TRAFFIC = {
+    "kernel": "k_cocg_spmv_dot<double>",
+    "source": "paper_0704_2344_amd/csrc/krylov_kernels.hip",
+    "sha256": "6d849109ec95ee7af1c6fe339745813aec18672d5adfcd1f1c9533e118b41834",
+    "fetch_kib": 54992.39, "write_kib": 1426.29,
+    "copy_fetch_kib": 524296.30, "copy_write_kib": 1048576.06, "copy_bytes": 1 << 30,
+}
+
+
+def measured_traffic():
+    """Bytes per launch of the dominant kernel, or None if its source has
+    changed since the counters were taken."""
+    import hashlib
+    m = MEASURED_TRAFFIC
+    with open(os.path.join(ROOT, m["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != m["sha256"]:
+            return None
+    fetch_scale = m["copy_bytes"] / (m["copy_fetch_kib"] * 1024)
+    write_scale = m["copy_bytes"] / (m["copy_write_kib"] * 1024)
+    return m["fetch_kib"] * 1024 * fetch_scale + m["write_kib"] * 1024 * write_scale
+
 
 def spmv_bytes(nn, nnzb, val_bytes, vec_bytes):
     """Algorithmic bytes of one block SpMV: every 3x3 block (9 complex values
     + one int32 column index) read once, the row pointers, x read once and y
     written once."""
     return nnzb * (9 * val_bytes + 4) + 4 * (nn + 1) + 2 * 3 * nn * vec_bytes
+
+
+def spmm_bytes(nn, nnzb, ncols):
+    """Algorithmic bytes of one batched SpMM: the complex128 matrix and its
+    column indices read once, the row pointers, the complex64 directions read
+    once and the complex128 products written once, for ncols columns."""
+    return nnzb * (9 * 16 + 4) + 4 * (nn + 1) + 3 * nn * ncols * (8 + 16)
+
+
+def serving_leg(ctx, F, W, n_requests, rate, n_hi):
+    """Replay a Poisson request stream in real time through the server (two
+    precisions) and through the plain FP64 solver one request at a time."""
+    reqs = W.serving_stream(n_requests=n_requests, rate_per_s=rate, seed=46, n_lo=10, n_hi=n_hi, nrhs_hi=4)
+    n_rhs = sum(len(r.waves) for r in reqs)
+    out = {"workload": (f"{n_requests} requests of the seeded serving stream (Poisson, {rate:g}/s), meshes n^3 "
+                        f"with n in [10, {n_hi}], 1-4 waves each ({n_rhs} right-hand sides), PEC box or sphere, "
+                        f"k0 in [pi, 4 pi] at 10 nodes per wavelength, rtol 1e-6")}
+    # warm the kernels and the allocator
+    srv = F.Server(ctx)
+    p0, w0 = reqs[0].problem, reqs[0].waves
+    t = srv.submit(p0, w0, precision=F.FEMH_FP64, rtol=1e-6)
+    srv.poll(t, len(w0), None, want_field=False)
+    srv.close()
+    for name, prec in (("server_mixed_matrix", F.FEMH_MIXED_MATRIX), ("server_fp64", F.FEMH_FP64)):
+        srv = F.Server(ctx)
+        t0 = time.perf_counter()
+        tickets = []
+        for r in reqs:
+            d = t0 + r.arrival_s - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets.append(srv.submit(r.problem, r.waves, precision=prec, rtol=1e-6))
+        bad = 0
+        for r, tk in zip(reqs, tickets):
+            st, _, _ = srv.poll(tk, len(r.waves), None, want_field=False)
+            bad += st != F.FEMH_OK
+        el = time.perf_counter() - t0
+        rep = srv.report()
+        srv.close()
+        out[name] = {"requests_per_s": rep["requests_per_second"], "rhs_per_s": rep["rhs_per_second"],
+                     "p50_s": rep["p50_seconds"], "p99_s": rep["p99_seconds"], "failed": bad,
+                     "wall_s": el, "peak_resident_bytes": rep["peak_resident_bytes"]}
+    # plain FP64 solver, one request at a time in arrival order
+    import torch
+    lat = []
+    bad = 0
+    t0 = time.perf_counter()
+    first = None
+    for r in reqs:
+        d = t0 + r.arrival_s - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        if first is None:
+            first = time.perf_counter()
+        P = F.Problem(ctx, r.problem)
+        o = torch.zeros(P.grid_shape(len(r.waves)), dtype=torch.complex128, device="cuda")
+        _, st = P.solve_dev(r.waves, o, precision=F.FEMH_FP64, rtol=1e-6)
+        torch.cuda.synchronize()
+        P.close()
+        bad += st != F.FEMH_OK
+        lat.append(time.perf_counter() - (t0 + r.arrival_s))
+    span = time.perf_counter() - first
+    out["plain_fp64_sequential"] = {"requests_per_s": n_requests / span, "rhs_per_s": n_rhs / span,
+                                    "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                                    "failed": bad}
+    out["server_mixed_vs_plain_fp64"] = out["server_mixed_matrix"]["rhs_per_s"] / out["plain_fp64_sequential"]["rhs_per_s"]
+    return out
 
 
 def cpu_baseline(prob, waves, iters_needed, sample_iters):
@@ -77,6 +177,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the 1e-6 comparison, HBM SpMV and batched legs")
     ap.add_argument("--cpu-sample-iters", type=int, default=300)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run the 1 GiB copy probe (the denominator of the traffic scale factor)")
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-n-hi", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (asked for --gpus {args.gpus}); the multi-GPU path is a design "
@@ -133,6 +238,7 @@ def main():
     avg = sec[0] / max(cnt[0], 1)
     achieved = b128 / avg / 1e9
 
+    traffic = measured_traffic()
     result = {
         "metric": "block SpMV GB/s (% HBM peak); solves/s + p99 latency at 1e-6, mixed vs FP64",
         "value": value,
@@ -155,11 +261,15 @@ def main():
         "solve": {"iters": st64["iters"], "restarts": st64["outer_iters"], "rel_residual": st64["rel_residual"],
                   "solve_s": st64["seconds"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "traffic_over_algorithmic": traffic / b128 if traffic else None,
                      "kernel": "k_cocg_spmv_dot<double> (complex128 block SpMV + p^T A p)",
                      "bytes_per_launch": b128, "avg_launch_s": avg, "launches": cnt[0],
                      "note": "the 111 MB complex128 matrix fits the 256 MB Infinity Cache"},
     }
+
+    if args.copy_probe:
+        result["copy_probe_GBps"] = ctx.bw_probe(1 << 30, 3)
 
     if not args.no_extras:
         cmp = {}
@@ -198,18 +308,39 @@ def main():
         p3, w3 = W.pec_sphere_batched(40)
         P3 = F.Problem(ctx, p3)
         o3 = torch.zeros(P3.grid_shape(64), dtype=torch.complex128, device=dev)
+        P3.solve_dev(w3[:2], o3[:2], batched=True, rtol=1e-3)   # tunes the SpMM, warms the graph path
         torch.cuda.synchronize()
         a = time.perf_counter()
-        stats3, st3 = P3.solve_dev(w3, o3, batched=True, precision=F.FEMH_MIXED, rtol=1e-6)
+        stats3, st3 = P3.solve_dev(w3, o3, batched=True, rtol=1e-6)
         torch.cuda.synchronize()
         el3 = time.perf_counter() - a
         its = [s["iters"] for s in stats3]
+        # the solver's SpMM (same kernel and grid), timed on its own
+        Xs = torch.randn(P3.n_unknowns, 64, dtype=torch.complex64, device=dev)
+        Ys = torch.zeros(P3.n_unknowns, 64, dtype=torch.complex128, device=dev)
+        t_spmm = P3.spmm_dev(Xs, Ys, reps=20)
+        del Xs, Ys
+        flops = P3.nnzb * 9 * 64 * 8
+        # single-RHS matrix-mixed solves of the first waves, for comparison
+        o1 = torch.zeros(P3.grid_shape(1), dtype=torch.complex128, device=dev)
+        ns = 4
+        a = time.perf_counter()
+        for wv in w3[:ns]:
+            P3.solve_dev([wv], o1, precision=F.FEMH_MIXED_MATRIX, rtol=1e-6)
+        torch.cuda.synchronize()
+        single_rhs_s = (time.perf_counter() - a) / ns
         result["batched"] = {"workload": "pec_sphere_40_b64: 40^3, PEC sphere R=1 wavelength, 64 RHS, to 1e-6",
                              "status": st3, "rhs_per_s": 64 / el3, "seconds": el3,
                              "iters_min": min(its), "iters_max": max(its),
                              "max_rel_residual": max(s["rel_residual"] for s in stats3),
-                             "spmm_tile": P3.spmm_tile()}
+                             "spmm_tile": P3.spmm_tile(), "spmm_us": t_spmm * 1e6,
+                             "spmm_GBps": spmm_bytes(P3.n_nodes, P3.nnzb, 64) / t_spmm / 1e9,
+                             "spmm_TFLOPs": flops / t_spmm / 1e12,
+                             "single_rhs_mixed_matrix_rhs_per_s": 1.0 / single_rhs_s,
+                             "speedup_vs_single": (64 / el3) * single_rhs_s}
         P3.close()
+
+        result["serving"] = serving_leg(ctx, F, W, args.serve_requests, args.serve_rate, args.serve_n_hi)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(prob, waves, st64["iters"], args.cpu_sample_iters)
