@@ -340,7 +340,8 @@ def main():
                              "speedup_vs_single": (64 / el3) * single_rhs_s}
         P3.close()
 
-        result["serving"] = serving_leg(ctx, F, W, args.serve_requests, args.serve_rate, args.serve_n_hi)
+        if args.serve_requests > 0:
+            result["serving"] = serving_leg(ctx, F, W, args.serve_requests, args.serve_rate, args.serve_n_hi)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(prob, waves, st64["iters"], args.cpu_sample_iters)

@@ -90,3 +90,26 @@ def test_cancel_and_admission(ctx):
     assert rep["peak_resident_bytes"] <= 64 << 20
     assert rep["rejected"] == 1 and rep["completed"] == 3
     srv.close()
+
+
+def test_three_precisions_grouped_match_plain_solves(ctx):
+    """Requests of all three precisions resident at once (three iteration
+    groups on one stream, members joining and leaving between chunks): each
+    field is bit-identical to femh_solve with the same options."""
+    reqs = _requests(5, 6, n_hi=16)
+    precs = [F.FEMH_FP64, F.FEMH_MIXED_MATRIX, F.FEMH_MIXED] * 2
+    srv = F.Server(ctx, max_slots=8, chunk_iters=16)
+    tickets = [srv.submit(p, w, precision=pr, rtol=1e-7) for (p, w), pr in zip(reqs, precs)]
+    fields = []
+    for (p, w), t in zip(reqs, tickets):
+        st, H, stats = srv.poll(t, len(w), _shape(p, len(w)))
+        assert st == F.FEMH_OK, stats
+        fields.append((H, stats))
+    srv.close()
+    for (p, w), pr, (H, stats) in zip(reqs, precs, fields):
+        P = F.Problem(ctx, p)
+        H1, s1, st1 = P.solve(w, precision=pr, rtol=1e-7, check_every=16)
+        assert st1 == F.FEMH_OK
+        np.testing.assert_array_equal(H, H1)
+        assert [s["iters"] for s in stats] == [s["iters"] for s in s1]
+        P.close()
