@@ -121,6 +121,9 @@ __global__ void __launch_bounds__(kBT) k_bspmm_mfma(PatternDev pt, const float2*
 }
 
 // Same product with FP64 vector FMAs on the complex128 matrix (lane = column).
+// The row's column indices (at most 27) come in with one vector load and are
+// taken lane by lane with readlane, so each block costs one memory latency
+// (its x entries and its matrix values load together) instead of two.
 __global__ void __launch_bounds__(kBT) k_bspmm_vec(PatternDev pt, const double2* __restrict__ val,
                                                    const float2* __restrict__ P, double2* __restrict__ Q,
                                                    double* __restrict__ partials, const BatchScalars* sc) {
@@ -131,9 +134,10 @@ __global__ void __launch_bounds__(kBT) k_bspmm_vec(PatternDev pt, const double2*
   for (int r = wave_index(kBT / 64, nwaves); r < pt.nn; r += nwaves) {
     const int beg = uniform_int(pt.row_ptr[r]);
     const int end = uniform_int(pt.row_ptr[r + 1]);
+    const int cl = lane < end - beg ? pt.col_idx[beg + lane] : 0;
     double yr[3] = {0.0, 0.0, 0.0}, yi[3] = {0.0, 0.0, 0.0};
     for (int b = beg; b < end; ++b) {
-      const int c = uniform_int(pt.col_idx[b]);
+      const int c = __builtin_amdgcn_readlane(cl, b - beg);
       const double2* blk = val + (size_t)b * 9;
       const float2* xrow = P + (size_t)3 * c * kLD + lane;
       const float2 f0 = xrow[0], f1 = xrow[kLD], f2 = xrow[2 * kLD];
