@@ -200,12 +200,18 @@ int femh_solve_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* wave
 
 /* Batched right-hand sides: the nrhs (<= 64) columns advance together,
  * one block-sparse matrix times dense block (SpMM) per iteration, each
- * column with its own COCG scalars, FP64 iterate, residual and product
- * (directions stored in complex64), and reliable updates against the FP64
- * matrix to opts->rtol.  opts->precision is ignored; opts->inner_rtol
- * (default 1e-3) is the residual drop that triggers a column's update.
- * Device memory: four FP64 and one complex64 [n_unknowns][64] blocks
- * whatever nrhs is.  H_out_dev as in femh_solve_dev. */
+ * column with its own COCG scalars (section 3.1.5's conjugate gradient with
+ * Jacobi preconditioning, applied per column).  Every column's iterate,
+ * residual, direction and product are FP64.  opts->precision FEMH_FP64 (the
+ * default) multiplies by the complex128 matrix; FEMH_MIXED and
+ * FEMH_MIXED_MATRIX multiply by the complex64 matrix promoted inside FP64
+ * products, with reliable updates against the FP64 matrix to opts->rtol.
+ * opts->inner_rtol (default 1e-3) is the residual drop that triggers a
+ * column's update (its true residual replaces the recurrence's).
+ * Up to four right-hand sides use a narrow [n_unknowns][4] layout whose
+ * product reads each matrix value once for all columns; more use the
+ * [n_unknowns][64] layout.  Device memory: five complex128 blocks of that
+ * layout.  H_out_dev as in femh_solve_dev. */
 int femh_solve_batched_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves,
                            const femh_solve_opts* opts, femh_c128* H_out_dev,
                            femh_solve_stats* stats);
@@ -235,18 +241,21 @@ int femh_export_jacobi(const femh_problem* prob, femh_c128* dinv);
 int femh_spmv_dev(femh_problem* prob, int32_t precision, const void* x_dev, void* y_dev,
                   int32_t reps, double* avg_seconds);
 
-/* Y = A X for ncols (1..64) columns: X complex64 and Y complex128 device
- * arrays [n_unknowns][ncols] (column index fastest), the batched solver's
- * product (FP64 arithmetic on the complex128 matrix, or FP32 matrix-core
- * products per block summed in FP64, as tuned).  Timing as femh_spmv_dev. */
-int femh_spmm_dev(femh_problem* prob, int32_t ncols, const void* X_dev, void* Y_dev,
+/* Y = A X for ncols (1..64) columns: X and Y complex128 device arrays
+ * [n_unknowns][ncols] (column index fastest), the batched solver's wide
+ * product.  precision FEMH_FP64: the complex128 matrix, FP64 arithmetic;
+ * FEMH_MIXED_MATRIX: the complex64 matrix promoted inside FP64 arithmetic,
+ * or FP32 matrix-core products per 3x3 block summed in FP64 when tile kind
+ * 1 is set (complex64 matrix whatever precision says).  Timing as
+ * femh_spmv_dev. */
+int femh_spmm_dev(femh_problem* prob, int32_t precision, int32_t ncols, const void* X_dev, void* Y_dev,
                   int32_t reps, double* avg_seconds);
 
-/* The SpMM shape the batched solver uses for this problem: *kind = 0 FP64
- * vector FMAs on the complex128 matrix (the only kind the autotuner times,
- * over grid sizes, on the first batched product), 1 matrix cores (complex64
- * matrix, FP32 products per 3x3 block; only when set explicitly), -1 not
- * tuned yet; *blocks = workgroups of the launch. */
+/* The wide SpMM shape the batched solver uses for this problem: *kind = 0
+ * FP64 vector FMAs (the only kind the autotuner times, over grid sizes, on
+ * the problem's first wide product, with that product's matrix), 1
+ * matrix cores (FP32 products per 3x3 block; only when set explicitly), -1
+ * not tuned yet; *blocks = workgroups of the launch. */
 int femh_spmm_tile(const femh_problem* prob, int32_t* kind, int32_t* blocks);
 
 /* Override the autotuner's choice (kind 0 or 1; blocks a positive multiple

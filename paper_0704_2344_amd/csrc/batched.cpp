@@ -1,11 +1,12 @@
 // Host driver of the batched-RHS solve: every column runs its own COCG
-// recurrence, the columns sharing one SpMM per iteration.  Each column's
-// iterate, residual and product are FP64; its direction is stored in
-// complex64 (the SpMM's input).  When a column's residual has fallen by
-// inner_rtol below its largest value since the last update (or meets the
-// tolerance, or breaks down), its residual is replaced by the FP64 true
-// residual b - A x and the recurrence continues with the same direction
-// (restarts after a breakdown).
+// recurrence, the columns sharing one SpMM per iteration (the complex128
+// matrix for FEMH_FP64, else the complex64 matrix promoted inside FP64
+// products); each column's iterate, residual, direction and product are
+// FP64.  When a column's residual has fallen by inner_rtol below its
+// largest value since the last update (or meets the tolerance, or breaks
+// down), its residual is replaced by the FP64 true residual b - A x and the
+// recurrence continues with the same direction (after a breakdown it takes
+// a minimal-residual step and restarts from the preconditioned residual).
 //
 // One iteration = SpMM + per-column alpha + update + per-column beta +
 // direction update (5 kernels).  A chunk of `check_every` iterations is
@@ -16,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 
 #include "internal.h"
@@ -24,7 +26,7 @@ namespace femh {
 
 namespace {
 
-constexpr size_t kPartialBytes = 2048 * 64 * 4 * sizeof(double);  // [blocks][64][4] doubles
+constexpr size_t kPartialBytes = 2048 * 64 * 4 * sizeof(double);  // [blocks][ld][4] doubles, ld <= 64
 
 struct Scratch {
   Ctx* ctx;
@@ -41,9 +43,10 @@ struct Scratch {
   }
 };
 
-// Process-wide tuning cache: (CU count, log2 of block rows) -> tile.
+// Process-wide tuning cache: (CU count, log2 of block rows, complex128
+// matrix) -> tile.
 std::mutex g_tune_mu;
-std::map<std::pair<int, int>, BatchTile> g_tune;
+std::map<std::tuple<int, int, bool>, BatchTile> g_tune;
 
 int ilog2(int64_t v) {
   int l = 0;
@@ -56,10 +59,11 @@ int ilog2(int64_t v) {
 
 }  // namespace
 
-int autotune_spmm(Problem* P, const float2* Pv, double2* Qv, double* partials, const BatchScalars* sc) {
+int autotune_spmm(Problem* P, const double2* val64, const double2* Pv, double2* Qv, double* partials,
+                  const BatchScalars* sc) {
   if (P->tile.kind >= 0) return FEMH_OK;
   Ctx* c = P->ctx;
-  const std::pair<int, int> key(c->n_cu, ilog2(P->pat.nn));
+  const std::tuple<int, int, bool> key(c->n_cu, ilog2(P->pat.nn), val64 != nullptr);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune.find(key);
@@ -74,7 +78,7 @@ int autotune_spmm(Problem* P, const float2* Pv, double2* Qv, double* partials, c
   FEMH_TRY_HIP(hipEventCreate(&e0));
   FEMH_TRY_HIP(hipEventCreate(&e1));
   // Only the FP64 vector kernel is a candidate: the matrix-core kernel's
-  // FP32 block products stall indefinite systems (explicit request only).
+  // FP64 block products stall indefinite systems (explicit request only).
   float best = 1e30f;
   BatchTile best_tile{0, k::batched_blocks_for(P->pat.nn, c->n_cu, 8)};
   int best_per_cu = 8;
@@ -83,9 +87,9 @@ int autotune_spmm(Problem* P, const float2* Pv, double2* Qv, double* partials, c
   for (int kind : kinds)
     for (int pc : per_cus) {
       BatchTile t{kind, k::batched_blocks_for(P->pat.nn, c->n_cu, pc)};
-      FEMH_TRY_HIP(k::bspmm(s, P->pat, P->val64, P->val32, Pv, Qv, partials, sc, t));  // warm
+      FEMH_TRY_HIP(k::bspmm(s, P->pat, P->val32, val64, Pv, Qv, partials, sc, t));  // warm
       FEMH_TRY_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) FEMH_TRY_HIP(k::bspmm(s, P->pat, P->val64, P->val32, Pv, Qv, partials, sc, t));
+      for (int r = 0; r < 3; ++r) FEMH_TRY_HIP(k::bspmm(s, P->pat, P->val32, val64, Pv, Qv, partials, sc, t));
       FEMH_TRY_HIP(hipEventRecord(e1, s));
       FEMH_TRY_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -109,18 +113,25 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
   Ctx* c = P->ctx;
   hipStream_t s = c->stream;
   const int64_t n = 3 * (int64_t)P->pat.nn;
-  const size_t v64 = 16 * (size_t)n * 64, v32 = 8 * (size_t)n * 64;
+  // narrow layout for up to four right-hand sides, wide otherwise
+  const int ld = nrhs <= 4 ? 4 : 64;
+  // FEMH_FP64: the complex128 matrix in the product; otherwise the
+  // complex64 matrix promoted
+  const double2* val64 = o.precision == FEMH_FP64 ? P->val64 : nullptr;
+  const size_t v64 = 16 * (size_t)n * ld;
   Scratch W(c);
   double2* B64 = (double2*)W.get(v64);
   double2* X64 = (double2*)W.get(v64);
   double2* R64 = (double2*)W.get(v64);
-  float2* P32 = (float2*)W.get(v32);
+  double2* P64 = (double2*)W.get(v64);
   double2* Q64 = (double2*)W.get(v64);
   double* partials = (double*)W.get(kPartialBytes);
   BatchScalars* sc = (BatchScalars*)W.get(sizeof(BatchScalars));
   BatchPlan* plan = (BatchPlan*)W.get(sizeof(BatchPlan));
+  BatchPlan* plan_mr = (BatchPlan*)W.get(sizeof(BatchPlan));
+  BatchScalars* run_all = (BatchScalars*)W.get(sizeof(BatchScalars));
   double* rr64 = (double*)W.get(64 * sizeof(double));
-  if (!B64 || !X64 || !R64 || !P32 || !Q64 || !partials || !sc || !plan || !rr64) {
+  if (!B64 || !X64 || !R64 || !P64 || !Q64 || !partials || !sc || !plan || !plan_mr || !run_all || !rr64) {
     set_error("device allocation failed (batched workspace)");
     return FEMH_E_OOM;
   }
@@ -136,7 +147,7 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
     FEMH_TRY_HIP(hipStreamSynchronize(s));
     dinv = ones;
   }
-  const int vblocks = k::batched_vec_blocks(n);
+  const int vblocks = k::batched_vec_blocks(n, ld);
   const int rblocks = k::batched_blocks_for(P->pat.nn, c->n_cu, 4);
 
   hipEvent_t t0, t1;
@@ -144,10 +155,10 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
   FEMH_TRY_HIP(hipEventCreate(&t1));
   FEMH_TRY_HIP(hipEventRecord(t0, s));
 
-  FEMH_TRY_HIP(k::to_block(s, n, nrhs, b, B64));
+  FEMH_TRY_HIP(k::to_block(s, n, ld, nrhs, b, B64));
   FEMH_TRY_HIP(hipMemsetAsync(X64, 0, v64, s));
-  FEMH_TRY_HIP(hipMemsetAsync(P32, 0, v32, s));
-  FEMH_TRY_HIP(k::bresidual64(s, P->pat, P->val64, X64, B64, R64, partials, rblocks, 64, rr64, nullptr));
+  FEMH_TRY_HIP(hipMemsetAsync(P64, 0, v64, s));
+  FEMH_TRY_HIP(k::bresidual64(s, P->pat, ld, P->val64, X64, B64, R64, partials, rblocks, rr64, nullptr));
   std::vector<double> hrr(64), bb(64);
   FEMH_TRY_HIP(hipMemcpyAsync(hrr.data(), rr64, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
   FEMH_TRY_HIP(hipStreamSynchronize(s));
@@ -177,20 +188,30 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
   }
   FEMH_TRY_HIP(hipMemcpyAsync(sc, hs, sizeof(*hs), hipMemcpyHostToDevice, s));
   FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
-  FEMH_TRY_HIP(k::brescale(s, n, R64, dinv, P32, partials, vblocks, 64, sc, plan));
+  FEMH_TRY_HIP(k::brescale(s, n, ld, R64, dinv, P64, partials, vblocks, sc, plan));
+  {
+    BatchScalars* ra = reinterpret_cast<BatchScalars*>(static_cast<char*>(c->pinned) + 8192);
+    static_assert(2 * sizeof(BatchScalars) <= 16384, "pinned scratch too small");
+    std::memset(ra, 0, sizeof(*ra));
+    ra->active = 1;
+    FEMH_TRY_HIP(hipMemcpyAsync(run_all, ra, sizeof(*ra), hipMemcpyHostToDevice, s));
+  }
   FEMH_TRY_HIP(hipStreamSynchronize(s));
-  FEMH_TRY(autotune_spmm(P, P32, Q64, partials, sc));
-  const BatchTile tile = P->tile;
+  BatchTile tile{2, P->spmv.blocks};  // narrow product: the single-RHS SpMV's grid
+  if (ld == 64) {
+    FEMH_TRY(autotune_spmm(P, val64, P64, Q64, partials, sc));
+    tile = P->tile;
+  }
 
   // one chunk of iterations, captured once
   auto launch_chunk = [&]() -> hipError_t {
     for (int i = 0; i < o.check_every; ++i) {
       hipError_t e;
-      if ((e = k::bspmm(s, P->pat, P->val64, P->val32, P32, Q64, partials, sc, tile)) != hipSuccess) return e;
-      if ((e = k::bred_alpha(s, partials, tile.blocks, 64, sc)) != hipSuccess) return e;
-      if ((e = k::bupdate(s, n, dinv, X64, R64, P32, Q64, partials, vblocks, sc)) != hipSuccess) return e;
-      if ((e = k::bred_beta(s, partials, vblocks, 64, sc)) != hipSuccess) return e;
-      if ((e = k::bpupdate(s, n, dinv, R64, P32, vblocks, sc, nullptr)) != hipSuccess) return e;
+      if ((e = k::bspmm(s, P->pat, P->val32, val64, P64, Q64, partials, sc, tile)) != hipSuccess) return e;
+      if ((e = k::bred_alpha(s, partials, tile.blocks, ld, sc)) != hipSuccess) return e;
+      if ((e = k::bupdate(s, n, ld, dinv, X64, R64, P64, Q64, partials, vblocks, sc)) != hipSuccess) return e;
+      if ((e = k::bred_beta(s, partials, vblocks, ld, sc)) != hipSuccess) return e;
+      if ((e = k::bpupdate(s, n, ld, dinv, R64, P64, vblocks, sc, nullptr)) != hipSuccess) return e;
     }
     return hipSuccess;
   };
@@ -241,7 +262,7 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
     }
     FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
     // true residual into the flagged columns only
-    FEMH_TRY_HIP(k::bresidual64(s, P->pat, P->val64, X64, B64, R64, partials, rblocks, 64, rr64, plan->action));
+    FEMH_TRY_HIP(k::bresidual64(s, P->pat, ld, P->val64, X64, B64, R64, partials, rblocks, rr64, plan->action));
     FEMH_TRY_HIP(hipMemcpyAsync(hrr.data(), rr64, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
     FEMH_TRY_HIP(hipStreamSynchronize(s));
     std::memset(&hp, 0, sizeof(hp));
@@ -264,16 +285,33 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
         hp.tol2[col] = o.rtol * o.rtol * bb[col];
       }
     }
+    // columns restarting after a breakdown first take a minimal-residual
+    // step, so the restart does not meet the same breakdown again
+    bool any_restart = false;
+    BatchPlan hm;
+    std::memset(&hm, 0, sizeof(hm));
+    for (int col = 0; col < 64; ++col)
+      if (hp.action[col] == 2) {
+        hm.action[col] = 2;
+        hm.tol2[col] = hp.tol2[col];
+        any_restart = true;
+      }
+    if (any_restart) {
+      FEMH_TRY_HIP(hipMemcpyAsync(plan_mr, &hm, sizeof(hm), hipMemcpyHostToDevice, s));
+      FEMH_TRY_HIP(k::brescale(s, n, ld, R64, dinv, P64, partials, vblocks, sc, plan_mr));
+      FEMH_TRY_HIP(k::bmr_step(s, P->pat, n, ld, P->val32, val64, X64, R64, P64, Q64, partials, vblocks, tile,
+                               run_all, sc, plan_mr));
+    }
     FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
-    FEMH_TRY_HIP(k::brescale(s, n, R64, dinv, P32, partials, vblocks, 64, sc, plan));
-    FEMH_TRY_HIP(k::bpupdate(s, n, dinv, R64, P32, vblocks, sc, plan->action));
+    FEMH_TRY_HIP(k::brescale(s, n, ld, R64, dinv, P64, partials, vblocks, sc, plan));
+    FEMH_TRY_HIP(k::bpupdate(s, n, ld, dinv, R64, P64, vblocks, sc, plan->action));
     FEMH_TRY_HIP(run_chunk());
   }
   FEMH_TRY_HIP(hipStreamSynchronize(s));
   (void)hipEventDestroy(ready);
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
-  FEMH_TRY_HIP(k::from_block(s, n, nrhs, X64, x));
+  FEMH_TRY_HIP(k::from_block(s, n, ld, nrhs, X64, x));
   FEMH_TRY_HIP(hipEventRecord(t1, s));
   FEMH_TRY_HIP(hipEventSynchronize(t1));
   float ms = 0.f;

@@ -265,11 +265,13 @@ int femh_solve_batched_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wa
     femh::set_error("%s", m.c_str());
     return st;
   }
-  // the batched recurrence is the matrix-mixed one (FP64 residuals,
-  // complex64 SpMM operands) whatever opts->precision says
+  // FP64 directions and residuals in every case; FEMH_FP64 multiplies by
+  // the complex128 matrix, any other precision by the complex64 matrix
   femh_solve_opts ob{};
   if (opts) ob = *opts;
-  ob.precision = FEMH_MIXED_MATRIX;
+  if (ob.precision != FEMH_FP64) ob.precision = FEMH_MIXED_MATRIX;
+  // both recurrences are FP64: reliable updates every three decades
+  if (ob.inner_rtol <= 0.0) ob.inner_rtol = 1e-3;
   const femh_solve_opts o = femh::opts_with_defaults(&ob);
   if (o.precond != FEMH_PRECOND_JACOBI && o.precond != FEMH_PRECOND_NONE) {
     femh::set_error("unknown preconditioner %d", o.precond);
@@ -293,29 +295,32 @@ int femh_solve_batched_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wa
   return rc;
 }
 
-int femh_spmm_dev(femh_problem* p, int32_t ncols, const void* X, void* Y, int32_t reps, double* avg_seconds) {
+int femh_spmm_dev(femh_problem* p, int32_t precision, int32_t ncols, const void* X, void* Y, int32_t reps,
+                  double* avg_seconds) {
   femh::clear_error();
-  if (!p || !X || !Y || reps < 1 || ncols < 1 || ncols > 64) {
-    femh::set_error("bad spmm arguments (1 <= ncols <= 64, reps >= 1)");
+  if (!p || !X || !Y || reps < 1 || ncols < 1 || ncols > 64 ||
+      (precision != FEMH_FP64 && precision != FEMH_MIXED_MATRIX)) {
+    femh::set_error("bad spmm arguments (precision FP64 or MIXED_MATRIX, 1 <= ncols <= 64, reps >= 1)");
     return FEMH_E_INVALID;
   }
+  const double2* val64 = precision == FEMH_FP64 ? p->val64 : nullptr;
   Ctx* c = p->ctx;
   hipStream_t s = c->stream;
   const int64_t n = 3 * (int64_t)p->pat.nn;
   const bool direct = ncols == 64;
-  DevTmp xp(c, direct ? 16 : 8 * (size_t)n * 64), yp(c, direct ? 16 : 16 * (size_t)n * 64);
+  DevTmp xp(c, direct ? 16 : 16 * (size_t)n * 64), yp(c, direct ? 16 : 16 * (size_t)n * 64);
   DevTmp part(c, 2048 * 64 * 4 * sizeof(double)), scd(c, sizeof(femh::BatchScalars));
   if (!xp.p || !yp.p || !part.p || !scd.p) {
     femh::set_error("device allocation failed (spmm)");
     return FEMH_E_OOM;
   }
-  const float2* Xd = (const float2*)X;
+  const double2* Xd = (const double2*)X;
   double2* Yd = (double2*)Y;
   if (!direct) {
-    FEMH_TRY_HIP(hipMemsetAsync(xp.p, 0, 8 * (size_t)n * 64, s));
-    FEMH_TRY_HIP(hipMemcpy2DAsync(xp.p, 64 * 8, X, (size_t)ncols * 8, (size_t)ncols * 8, (size_t)n,
+    FEMH_TRY_HIP(hipMemsetAsync(xp.p, 0, 16 * (size_t)n * 64, s));
+    FEMH_TRY_HIP(hipMemcpy2DAsync(xp.p, 64 * 16, X, (size_t)ncols * 16, (size_t)ncols * 16, (size_t)n,
                                   hipMemcpyDeviceToDevice, s));
-    Xd = (const float2*)xp.p;
+    Xd = (const double2*)xp.p;
     Yd = (double2*)yp.p;
   }
   femh::BatchScalars* hs = reinterpret_cast<femh::BatchScalars*>(c->pinned);
@@ -323,14 +328,14 @@ int femh_spmm_dev(femh_problem* p, int32_t ncols, const void* X, void* Y, int32_
   hs->active = 1;
   FEMH_TRY_HIP(hipMemcpyAsync(scd.p, hs, sizeof(*hs), hipMemcpyHostToDevice, s));
   FEMH_TRY_HIP(hipStreamSynchronize(s));
-  FEMH_TRY(femh::autotune_spmm(p, Xd, Yd, (double*)part.p, (const femh::BatchScalars*)scd.p));
+  FEMH_TRY(femh::autotune_spmm(p, val64, Xd, Yd, (double*)part.p, (const femh::BatchScalars*)scd.p));
   hipEvent_t e0, e1;
   FEMH_TRY_HIP(hipEventCreate(&e0));
   FEMH_TRY_HIP(hipEventCreate(&e1));
   FEMH_TRY_HIP(hipEventRecord(e0, s));
   for (int i = 0; i < reps; ++i)
-    FEMH_TRY_HIP(femh::k::bspmm(s, p->pat, p->val64, p->val32, Xd, Yd, (double*)part.p, (const femh::BatchScalars*)scd.p,
-                                p->tile));
+    FEMH_TRY_HIP(femh::k::bspmm(s, p->pat, p->val32, val64, Xd, Yd, (double*)part.p,
+                                (const femh::BatchScalars*)scd.p, p->tile));
   FEMH_TRY_HIP(hipEventRecord(e1, s));
   FEMH_TRY_HIP(hipEventSynchronize(e1));
   float ms = 0;

@@ -109,7 +109,8 @@ struct BatchPlan {
   double tol2[64];    // recursive tolerance (absolute ||r||^2)
 };
 
-// SpMM tile choice: kind 1 = matrix cores, 0 = vector FMAs; blocks = grid.
+// SpMM tile choice: kind 0 = vector FMAs, 1 = matrix cores (both 64
+// columns), 2 = narrow product (4 columns); blocks = grid.
 struct BatchTile {
   int kind;
   int blocks;
@@ -118,26 +119,36 @@ struct BatchTile {
 // --------------------------------------------------------------- launchers
 namespace k {
 
-// ---- batched right-hand sides ([n][64] complex layout)
+// ---- batched right-hand sides ([n][ld] complex layout, ld = 4 or 64)
 int batched_blocks_for(int32_t nn, int n_cu, int per_cu);
-int batched_vec_blocks(int64_t n);
-// per-column partial sums are FP64: partials hold [blocks][64][4] doubles
-// kind 0 reads the complex128 matrix, kind 1 the complex64 one; Q is FP64
-hipError_t bspmm(hipStream_t st, const PatternDev& pt, const double2* val64, const float2* val32, const float2* P,
+int batched_vec_blocks(int64_t n, int ld);
+// per-column partial sums are FP64: partials hold [blocks][ld][4] doubles
+// The matrix times FP64 directions: the complex128 values when val64 is not
+// null, else the complex64 values promoted, FP64 products.  tile.kind 0:
+// vector FMAs (ld 64), 1: matrix cores, FP32 products per block of the
+// complex64 matrix (ld 64), 2: narrow product (ld 4)
+hipError_t bspmm(hipStream_t st, const PatternDev& pt, const float2* val32, const double2* val64, const double2* P,
                  double2* Q, double* partials, const BatchScalars* sc, BatchTile tile);
-hipError_t bred_alpha(hipStream_t st, const double* partials, int nblocks, int ncols, BatchScalars* sc);
-hipError_t bupdate(hipStream_t st, int64_t n, const double2* dinv, double2* X, double2* R, const float2* P,
+hipError_t bred_alpha(hipStream_t st, const double* partials, int nblocks, int ld, BatchScalars* sc);
+hipError_t bupdate(hipStream_t st, int64_t n, int ld, const double2* dinv, double2* X, double2* R, const double2* P,
                    const double2* Q, double* partials, int blocks, const BatchScalars* sc);
-hipError_t bred_beta(hipStream_t st, const double* partials, int nblocks, int ncols, BatchScalars* sc);
-hipError_t bpupdate(hipStream_t st, int64_t n, const double2* dinv, const double2* R, float2* P, int blocks,
+hipError_t bred_beta(hipStream_t st, const double* partials, int nblocks, int ld, BatchScalars* sc);
+hipError_t bpupdate(hipStream_t st, int64_t n, int ld, const double2* dinv, const double2* R, double2* P, int blocks,
                     const BatchScalars* sc, const int32_t* only);
-hipError_t bresidual64(hipStream_t st, const PatternDev& pt, const double2* val, const double2* X,
-                       const double2* B, double2* R, double* partials, int blocks, int ncols, double* rr64,
+hipError_t bresidual64(hipStream_t st, const PatternDev& pt, int ld, const double2* val, const double2* X,
+                       const double2* B, double2* R, double* partials, int blocks, double* rr64,
                        const int32_t* mask);
-hipError_t brescale(hipStream_t st, int64_t n, const double2* R, const double2* dinv, float2* P,
-                    double* partials, int blocks, int ncols, BatchScalars* sc, const BatchPlan* plan);
-hipError_t to_block(hipStream_t st, int64_t n, int nrhs, const double2* b, double2* B);
-hipError_t from_block(hipStream_t st, int64_t n, int nrhs, const double2* X, double2* x);
+hipError_t brescale(hipStream_t st, int64_t n, int ld, const double2* R, const double2* dinv, double2* P,
+                    double* partials, int blocks, BatchScalars* sc, const BatchPlan* plan);
+// Minimal-residual step (x += omega p, r -= omega A p, omega = (Ap)^H r /
+// |Ap|^2) for the columns with plan->action == 2, whose P holds D^-1 r;
+// run_all is a scalar block with active = 1 so the product always runs.
+hipError_t bmr_step(hipStream_t st, const PatternDev& pt, int64_t n, int ld, const float2* val32,
+                    const double2* val64, double2* X,
+                    double2* R, const double2* P, double2* Q, double* partials, int blocks, BatchTile tile,
+                    const BatchScalars* run_all, BatchScalars* sc, const BatchPlan* plan);
+hipError_t to_block(hipStream_t st, int64_t n, int ld, int nrhs, const double2* b, double2* B);
+hipError_t from_block(hipStream_t st, int64_t n, int ld, int nrhs, const double2* X, double2* x);
 
 // Exclusive prefix sum of n int32 (n >= 0); *total (device) gets the sum.
 // tmp must hold scan_tmp_ints(n) ints.
@@ -307,7 +318,11 @@ int solve_single(Problem* P, const double2* b, double2* x, const femh_solve_opts
 int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh_solve_opts& o,
                   femh_solve_stats* st);
 // Pick the SpMM tile for a problem (timed candidates), cached on the problem.
-int autotune_spmm(Problem* P, const float2* Pv, double2* Qv, double* partials, const BatchScalars* sc);
+// Times the wide vector SpMM over grid sizes with the given matrix (val64
+// non-null: complex128) unless the problem's tile is set; cached per (CU
+// count, log2 of block rows, matrix precision).
+int autotune_spmm(Problem* P, const double2* val64, const double2* Pv, double2* Qv, double* partials,
+                  const BatchScalars* sc);
 
 // Single-RHS solve as a non-blocking state machine (one code path for
 // femh_solve and the server).  step() queues the work its phase allows and

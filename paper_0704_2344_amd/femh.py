@@ -136,7 +136,7 @@ SIGNATURES = {
     "femh_export_rhs": (C.c_int, [P, I32, C.POINTER(femh_plane_wave), P]),
     "femh_export_jacobi": (C.c_int, [P, P]),
     "femh_spmv_dev": (C.c_int, [P, I32, P, P, I32, PD]),
-    "femh_spmm_dev": (C.c_int, [P, I32, P, P, I32, PD]),
+    "femh_spmm_dev": (C.c_int, [P, I32, I32, P, P, I32, PD]),
     "femh_spmm_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
     "femh_spmm_set_tile": (C.c_int, [P, I32, I32]),
     "femh_bw_probe": (C.c_int, [P, I64, I32, PD]),
@@ -458,9 +458,10 @@ class Problem:
     def spmm_set_tile(self, kind, blocks):
         check(self.lib.femh_spmm_set_tile(self.handle, kind, blocks))
 
-    def spmm_dev(self, X, Y, reps=1):
+    def spmm_dev(self, X, Y, reps=1, precision=FEMH_MIXED_MATRIX):
         t = C.c_double()
-        check(self.lib.femh_spmm_dev(self.handle, X.shape[1], X.data_ptr(), Y.data_ptr(), reps, C.byref(t)))
+        check(self.lib.femh_spmm_dev(self.handle, precision, X.shape[1], X.data_ptr(), Y.data_ptr(), reps,
+                                     C.byref(t)))
         return t.value
 
 

@@ -1,14 +1,16 @@
-"""GPU parity of the batched right-hand-side path (SpMM of complex64
-directions into FP64 products, per-column COCG with FP64 iterates and
-residuals, reliable updates).
+"""GPU parity of the batched right-hand-side path (per-column COCG with
+FP64 iterates, residuals and directions; the complex128 matrix, or the
+complex64 matrix promoted inside FP64 products with reliable updates).
 
-  SpMM, FP64 vector kernel   <= 1e-13 (|A| |X|) per entry vs the FP64 product
-                              of the complex128 matrix and the directions
+  SpMM, FP64 vector kernel   <= 1e-13 (|A| |X|) per entry vs the FP64
+                              product of the same matrix (complex128, or
+                              the complex64 values) and X
   SpMM, matrix-core kernel   <= 2e-6 (|A32| |X|) per entry vs the FP64 product
-                              of the complex64 operands (FP32 products within
-                              one 3x3 block, FP64 sums over blocks)
+                              of the complex64 matrix and X rounded to
+                              complex64 (FP32 products within one 3x3 block,
+                              FP64 sums over blocks)
   batched solve              each column within 1e-6 (relative L2) of the
-                              LU solution, and of the single-RHS mixed solve
+                              LU solution, and of the single-RHS solve
   full size (40^3, 64 RHS)   every column's backward error under the
                               oracle's matrix <= 1e-6
 """
@@ -45,20 +47,21 @@ def _bsr(P, c64):
     return sp.bsr_matrix((v, ci, rp), shape=(n, n)).tocsr()
 
 
-@pytest.mark.parametrize("kind", [1, 0])
+@pytest.mark.parametrize("kind,prec", [(1, F.FEMH_MIXED_MATRIX), (0, F.FEMH_MIXED_MATRIX), (0, F.FEMH_FP64)])
 @pytest.mark.parametrize("ncols", [64, 5])
-def test_spmm_matches_oracle(ctx, torch, kind, ncols):
+def test_spmm_matches_oracle(ctx, torch, kind, prec, ncols):
     prob, _ = W.pec_sphere_shell(n=12, radius=0.3, shell=0.1, seed=8)
     P = F.Problem(ctx, prob)
     P.spmm_set_tile(kind, 64)
     rng = np.random.default_rng(ncols)
-    X = (rng.standard_normal((P.n_unknowns, ncols)) + 1j * rng.standard_normal((P.n_unknowns, ncols))).astype(np.complex64)
+    X = rng.standard_normal((P.n_unknowns, ncols)) + 1j * rng.standard_normal((P.n_unknowns, ncols))
     Xt = torch.from_numpy(X).cuda()
     Yt = torch.zeros(X.shape, dtype=torch.complex128, device="cuda")
-    P.spmm_dev(Xt, Yt, reps=2)
+    P.spmm_dev(Xt, Yt, reps=2, precision=prec)
     Y = Yt.cpu().numpy()
-    A = _bsr(P, c64=kind == 1)
-    Xd = X.astype(np.complex128)
+    # the matrix-core kernel multiplies the complex64 values whatever the precision
+    A = _bsr(P, c64=prec != F.FEMH_FP64 or kind == 1)
+    Xd = X.astype(np.complex64).astype(np.complex128) if kind == 1 else X
     ref = A @ Xd
     bound = abs(A) @ abs(Xd)
     tol = 2e-6 if kind == 1 else 1e-13
@@ -67,7 +70,8 @@ def test_spmm_matches_oracle(ctx, torch, kind, ncols):
     P.close()
 
 
-def test_batched_solve_matches_lu_and_single(ctx, torch):
+@pytest.mark.parametrize("prec", [F.FEMH_FP64, F.FEMH_MIXED_MATRIX])
+def test_batched_solve_matches_lu_and_single(ctx, torch, prec):
     prob, waves = W.pec_sphere_batched(n=16, radius=0.4, nrhs=8, seed=3)
     A = fem.assemble(prob)
     B = fem.rhs(prob, waves)
@@ -75,10 +79,10 @@ def test_batched_solve_matches_lu_and_single(ctx, torch):
     Ho = fem.scatter_to_grid(prob, X)
     P = F.Problem(ctx, prob)
     out = torch.zeros(P.grid_shape(8), dtype=torch.complex128, device="cuda")
-    stats, st = P.solve_dev(waves, out, batched=True, precision=F.FEMH_MIXED, rtol=1e-9)
+    stats, st = P.solve_dev(waves, out, batched=True, precision=prec, rtol=1e-9)
     assert st == F.FEMH_OK, stats
     H = out.cpu().numpy()
-    Hs, stats1, st1 = P.solve(waves, precision=F.FEMH_MIXED, rtol=1e-9)
+    Hs, stats1, st1 = P.solve(waves, precision=prec, rtol=1e-9)
     assert st1 == F.FEMH_OK, stats1
     for r in range(8):
         err = np.linalg.norm(H[r] - Ho[r]) / np.linalg.norm(Ho[r])
@@ -86,6 +90,29 @@ def test_batched_solve_matches_lu_and_single(ctx, torch):
         d = np.linalg.norm(H[r] - Hs[r]) / np.linalg.norm(Hs[r])
         assert d <= 1e-6, (r, d)
         assert stats[r]["rel_residual"] <= 1e-9
+    P.close()
+
+
+@pytest.mark.parametrize("nrhs,prec", [(1, F.FEMH_FP64), (2, F.FEMH_FP64), (4, F.FEMH_FP64),
+                                       (3, F.FEMH_MIXED_MATRIX)])
+def test_narrow_batch_matches_lu(ctx, torch, nrhs, prec):
+    """Up to four right-hand sides take the narrow [n][4] layout and product:
+    each column within 1e-6 of the LU solution and to its residual."""
+    prob, waves = W.pec_sphere_batched(n=14, radius=0.35, nrhs=nrhs, seed=20 + nrhs)
+    A = fem.assemble(prob)
+    B = fem.rhs(prob, waves)
+    X = solve.sparse_solve(A, B)
+    Ho = fem.scatter_to_grid(prob, X)
+    P = F.Problem(ctx, prob)
+    out = torch.zeros(P.grid_shape(nrhs), dtype=torch.complex128, device="cuda")
+    stats, st = P.solve_dev(waves, out, batched=True, precision=prec, rtol=1e-9)
+    assert st == F.FEMH_OK, stats
+    H = out.cpu().numpy()
+    mask = fem.Mesh(prob).node_active
+    for r in range(nrhs):
+        assert np.linalg.norm(H[r] - Ho[r]) / np.linalg.norm(Ho[r]) <= 1e-6, (r, stats[r])
+        x = H[r][mask].reshape(-1)
+        assert solve.residual(A, x, B[:, r]) <= 1e-9 * 1.001
     P.close()
 
 
@@ -106,12 +133,13 @@ def test_batched_ragged_column_count(ctx, torch):
 
 def test_pec_sphere_40_b64_full_size(ctx, torch):
     """The batched workload: 40^3 mesh, PEC sphere of radius one wavelength,
-    64 directions, mixed precision to 1e-6 per column; each column's
-    backward error under the oracle's matrix and right-hand side."""
+    64 directions, FP64 (the bench's configuration) to 1e-6 per column;
+    each column's backward error under the oracle's matrix and right-hand
+    side."""
     prob, waves = W.pec_sphere_batched(40)
     P = F.Problem(ctx, prob)
     out = torch.zeros(P.grid_shape(64), dtype=torch.complex128, device="cuda")
-    stats, st = P.solve_dev(waves, out, batched=True, precision=F.FEMH_MIXED, rtol=1e-6)
+    stats, st = P.solve_dev(waves, out, batched=True, precision=F.FEMH_FP64, rtol=1e-6)
     assert st == F.FEMH_OK, [s for s in stats if s["status"] != 0][:3]
     A = fem.assemble(prob)
     B = fem.rhs(prob, waves)
