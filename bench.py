@@ -52,9 +52,9 @@ HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E datasheet
 MEASURED_TRAFFIC = {
     "kernel": "k_cocg_spmv_dot<double>",
     "source": "paper_0704_2344_amd/csrc/krylov_kernels.hip",
-    "sha256": "6d849109ec95ee7af1c6fe339745813aec18672d5adfcd1f1c9533e118b41834",
-    "fetch_kib": 54992.39, "write_kib": 1426.29,
-    "copy_fetch_kib": 524296.30, "copy_write_kib": 1048576.06, "copy_bytes": 1 << 30,
+    "sha256": "d3465288d794d8b165bd0e6265263945b2206fad701c777de27fa35c5f1ff344",
+    "fetch_kib": 54994.68, "write_kib": 1426.29,
+    "copy_fetch_kib": 524297.02, "copy_write_kib": 1048576.12, "copy_bytes": 1 << 30,
 }
 
 
@@ -177,7 +177,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cmp-steps", type=int, default=3, help="steps per solver in the 1e-6 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the 1e-6 comparison, HBM SpMV and batched legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip every leg but the headline")
+    ap.add_argument("--extras", default="cmp,hbm,batched,serving",
+                    help="legs after the headline, comma-separated subset of cmp,hbm,batched,serving")
+    ap.add_argument("--batched-singles", type=int, default=4,
+                    help="single-RHS solves per precision timed beside the batched leg (0 skips them)")
     ap.add_argument("--cpu-sample-iters", type=int, default=300)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run the 1 GiB copy probe (the denominator of the traffic scale factor)")
@@ -273,7 +277,12 @@ def main():
     if args.copy_probe:
         result["copy_probe_GBps"] = ctx.bw_probe(1 << 30, 3)
 
-    if not args.no_extras:
+    legs = set() if args.no_extras else {x for x in args.extras.split(",") if x}
+    unknown = legs - {"cmp", "hbm", "batched", "serving"}
+    if unknown:
+        raise SystemExit(f"unknown --extras legs: {sorted(unknown)}")
+
+    if "cmp" in legs:
         cmp = {}
         for name, prec in (("fp64", F.FEMH_FP64), ("mixed", F.FEMH_MIXED), ("mixed_matrix", F.FEMH_MIXED_MATRIX)):
             step(prec, 1e-6)
@@ -285,6 +294,7 @@ def main():
             cmp["fp64"]["solves_per_s"]
         result["at_1e6"] = cmp
 
+    if "hbm" in legs:
         # block SpMV on a matrix larger than the Infinity Cache
         p2, _ = W.pec_sphere_shell(60)
         P2 = F.Problem(ctx, p2)
@@ -306,6 +316,7 @@ def main():
         result["spmv_hbm"] = hb
         P2.close()
 
+    if "batched" in legs:
         # batched right-hand sides
         p3, w3 = W.pec_sphere_batched(40)
         P3 = F.Problem(ctx, p3)
@@ -326,9 +337,11 @@ def main():
         flops = P3.nnzb * 9 * 64 * 8
         # single-RHS solves of the first waves (matrix-mixed and plain FP64), for comparison
         o1 = torch.zeros(P3.grid_shape(1), dtype=torch.complex128, device=dev)
-        ns = 4
-        single = {}
+        ns = args.batched_singles
+        single = {"mixed_matrix": None, "fp64": None}
         for name, prec in (("mixed_matrix", F.FEMH_MIXED_MATRIX), ("fp64", F.FEMH_FP64)):
+            if ns <= 0:
+                break
             torch.cuda.synchronize()
             a = time.perf_counter()
             for wv in w3[:ns]:
@@ -343,13 +356,14 @@ def main():
                              "spmm_tile": P3.spmm_tile(), "spmm_us": t_spmm * 1e6,
                              "spmm_GBps": spmm_bytes(P3.n_nodes, P3.nnzb, 64) / t_spmm / 1e9,
                              "spmm_TFLOPs": flops / t_spmm / 1e12,
-                             "single_rhs_mixed_matrix_rhs_per_s": 1.0 / single["mixed_matrix"],
-                             "single_rhs_fp64_rhs_per_s": 1.0 / single["fp64"],
-                             "speedup_vs_single_fp64": (64 / el3) * single["fp64"]}
+                             "single_rhs_mixed_matrix_rhs_per_s":
+                                 1.0 / single["mixed_matrix"] if single["mixed_matrix"] else None,
+                             "single_rhs_fp64_rhs_per_s": 1.0 / single["fp64"] if single["fp64"] else None,
+                             "speedup_vs_single_fp64": (64 / el3) * single["fp64"] if single["fp64"] else None}
         P3.close()
 
-        if args.serve_requests > 0:
-            result["serving"] = serving_leg(ctx, F, W, args.serve_requests, args.serve_rate, args.serve_n_hi)
+    if "serving" in legs and args.serve_requests > 0:
+        result["serving"] = serving_leg(ctx, F, W, args.serve_requests, args.serve_rate, args.serve_n_hi)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(prob, waves, st64["iters"], args.cpu_sample_iters)

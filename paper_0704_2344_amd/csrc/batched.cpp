@@ -59,8 +59,47 @@ int ilog2(int64_t v) {
 
 }  // namespace
 
+// Wide SpMM traversal order: block rows sorted by (y slab, z, y, x), a slab
+// being kSlabY node rows in y.  Consecutive positions then sweep z through
+// one thin slab, and a row's neighbours one node plane away in z (the 18 of
+// its 27 blocks in the planes below and above) were gathered about
+// 2 kSlabY (nx + 1) rows earlier, within what one XCD's L2 still holds; in
+// plain (z, y, x) order they lie a whole plane away and are fetched again.
+// On the 40^3 sphere with 64 columns: 364 us per product against 397 us in
+// plain order (slabs of 2, 4, 8, 16 rows: 390, 368, 364, 368 us).
+constexpr int kSlabY = 8;
+
+int ensure_row_order(Problem* P) {
+  if (P->row_order) return FEMH_OK;
+  const int32_t nn = P->pat.nn;
+  const int gx = P->mesh.nx + 1, gy = P->mesh.ny + 1, gz = P->mesh.nz + 1;
+  std::vector<int32_t> grid((size_t)nn), order((size_t)nn);
+  FEMH_TRY_HIP(hipMemcpy(grid.data(), P->node_grid, sizeof(int32_t) * nn, hipMemcpyDeviceToHost));
+  // stable counting sort of the rows (already in (z, y, x) order) by (slab, z)
+  const int slabs = (gy + kSlabY - 1) / kSlabY;
+  std::vector<int64_t> start((size_t)slabs * gz + 1, 0);
+  auto bucket = [&](int32_t g) {
+    const int64_t plane = (int64_t)gx * gy;
+    const int z = (int)(g / plane), y = (int)((g % plane) / gx);
+    return (int64_t)(y / kSlabY) * gz + z;
+  };
+  for (int32_t a = 0; a < nn; ++a) ++start[bucket(grid[a]) + 1];
+  for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+  for (int32_t a = 0; a < nn; ++a) order[start[bucket(grid[a])]++] = a;
+  int32_t* d = (int32_t*)P->alloc(sizeof(int32_t) * nn);
+  if (!d) {
+    set_error("device allocation failed (row order)");
+    return FEMH_E_OOM;
+  }
+  FEMH_TRY_HIP(hipMemcpy(d, order.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice));
+  P->row_order = d;
+  P->pat.row_order = d;
+  return FEMH_OK;
+}
+
 int autotune_spmm(Problem* P, const double2* val64, const double2* Pv, double2* Qv, double* partials,
                   const BatchScalars* sc) {
+  FEMH_TRY(ensure_row_order(P));
   if (P->tile.kind >= 0) return FEMH_OK;
   Ctx* c = P->ctx;
   const std::tuple<int, int, bool> key(c->n_cu, ilog2(P->pat.nn), val64 != nullptr);

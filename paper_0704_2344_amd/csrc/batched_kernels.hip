@@ -146,8 +146,16 @@ __global__ void __launch_bounds__(kBT) k_bspmm_vec(PatternDev pt, const V* __res
   if (sc->active == 0) return;
   const int lane = threadIdx.x & 63;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  int nwaves;
-  for (int r = wave_index(kBT / 64, nwaves); r < pt.nn; r += nwaves) {
+  // XCD x (the workgroups b with b mod 8 = x; the grid is a multiple of 8)
+  // takes positions [x nn / 8, (x + 1) nn / 8) of the row order, its waves
+  // sweeping them front to back, so one XCD's L2 holds the gathered
+  // directions of a compact slab of the mesh.
+  const int xcd = blockIdx.x & 7;
+  const int wpx = (int)(gridDim.x >> 3) * (kBT / 64);
+  const int pend = (int)(((int64_t)pt.nn * (xcd + 1)) >> 3);
+  for (int pos = (int)(((int64_t)pt.nn * xcd) >> 3) + (int)(blockIdx.x >> 3) * (kBT / 64) + (threadIdx.x >> 6);
+       pos < pend; pos += wpx) {
+    const int r = pt.row_order ? uniform_int(pt.row_order[pos]) : pos;
     const int beg = uniform_int(pt.row_ptr[r]);
     const int end = uniform_int(pt.row_ptr[r + 1]);
     const int cl = lane < end - beg ? pt.col_idx[beg + lane] : 0;

@@ -58,6 +58,7 @@ struct PatternDev {
   const uint32_t* nbr_mask;  // [nn] 27-bit neighbour mask, bit = (dz+1)*9 + (dy+1)*3 + (dx+1)
   const int32_t* row_ptr;    // [nn + 1]
   const int32_t* col_idx;    // [nnzb]
+  const int32_t* row_order;  // [nn] block-row order of the wide SpMM, or null (built on its first use)
 };
 
 // COCG scalar block of one right-hand side, kept on the device so the
@@ -294,6 +295,7 @@ struct Problem {
   int64_t dev_bytes = 0;
   k::SpmvLaunch spmv{};
   BatchTile tile{-1, 0};  // autotuned SpMM shape (kind -1 = not tuned yet)
+  int32_t* row_order = nullptr;  // wide SpMM traversal order (device, [nn])
 
   std::vector<void*> owned;
   void* alloc(size_t bytes);  // tracked allocation, freed with the problem
@@ -323,6 +325,8 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
 // count, log2 of block rows, matrix precision).
 int autotune_spmm(Problem* P, const double2* val64, const double2* Pv, double2* Qv, double* partials,
                   const BatchScalars* sc);
+// Builds P->row_order (and P->pat.row_order) once per problem.
+int ensure_row_order(Problem* P);
 
 // Single-RHS solve as a non-blocking state machine (one code path for
 // femh_solve and the server).  step() queues the work its phase allows and

@@ -30,6 +30,8 @@ namespace {
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
+// entries per thread and grid sweep in the COCG update kernels
+constexpr int kPerThread = 2;
 
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
@@ -252,11 +254,30 @@ __device__ __forceinline__ void store_partials4(double (&v)[4], double* __restri
 }
 
 // Every workgroup re-reduces the producer's nin partials in one fixed order,
-// so all workgroups (and every run) see bit-identical totals.
+// so all workgroups (and every run) see bit-identical totals.  Producers
+// have at most 2048 workgroups: a thread's (up to) eight loads are issued
+// together, then summed in order.
 __device__ __forceinline__ void reduce_partials4(const double* __restrict__ partials, int nin, double (&t)[4]) {
   __shared__ double s_tot[4];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nin; b += kBlock)
+  double2 lo[8], hi[8];
+  const double2* p2 = reinterpret_cast<const double2*>(partials);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int b = threadIdx.x + k * kBlock;
+    lo[k] = b < nin ? p2[2 * (size_t)b] : make_double2(0.0, 0.0);
+    hi[k] = b < nin ? p2[2 * (size_t)b + 1] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (threadIdx.x + k * kBlock < nin) {
+      acc[0] += lo[k].x;
+      acc[1] += lo[k].y;
+      acc[2] += hi[k].x;
+      acc[3] += hi[k].y;
+    }
+  }
+  for (int b = threadIdx.x + 8 * kBlock; b < nin; b += kBlock)
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] += partials[(size_t)b * 4 + i];
   block_sum<double, 4>(acc);
@@ -352,6 +373,9 @@ __global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const V
 
 // alpha = rho / p^T q (re-reduced); x += alpha p; r -= alpha q;
 // partials of rho' = r^T z (z = D^-1 r, not stored), ||r||^2, ||z||^2.
+// A thread owns kPerThread entries kBlock apart per grid sweep; the first
+// sweep's operands and the scalars are loaded before the re-reduction,
+// which does not need them, so their latency overlaps it.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t n, const typename Cx<R>::T* __restrict__ dinv,
                                                         typename Cx<R>::T* __restrict__ x,
@@ -362,10 +386,29 @@ __global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t n, const typenam
                                                         double* __restrict__ pout, int par) {
   using C = typename Cx<R>::T;
   if (sc->done) return;
+  const double2 rho = sc->rho[par];
+  const double bd_tol = sc->bd_tol;
+  const int64_t stride = (int64_t)gridDim.x * kBlock * kPerThread;
+  int64_t i0 = (int64_t)blockIdx.x * kBlock * kPerThread + threadIdx.x;
+  C pv[kPerThread], qv[kPerThread], dv[kPerThread], xv[kPerThread], rv[kPerThread];
+  auto load = [&](int64_t b) {
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t i = b + (int64_t)k * kBlock;
+      if (i < n) {
+        pv[k] = p[i];
+        qv[k] = q[i];
+        dv[k] = dinv[i];
+        xv[k] = x[i];
+        rv[k] = r[i];
+      }
+    }
+  };
+  load(i0);
   double t[4];
   reduce_partials4(pin, nin, t);
   const double2 pq = make_double2(t[0], t[1]);
-  if (cabs2(pq) <= sc->bd_tol * sc->bd_tol * t[2] * t[3]) {
+  if (cabs2(pq) <= bd_tol * bd_tol * t[2] * t[3]) {
     // every workgroup reaches the same verdict; one records it
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->done = 3;
@@ -373,26 +416,32 @@ __global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t n, const typenam
     }
     return;
   }
-  const double2 alpha = cdiv(sc->rho[par], pq);
+  const double2 alpha = cdiv(rho, pq);
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->alpha = alpha;
   const R ar = (R)alpha.x, ai = (R)alpha.y;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-    const C pi = p[i], qi = q[i], di = dinv[i];
-    C xi = x[i], ri = r[i];
-    xi.x += ar * pi.x - ai * pi.y;
-    xi.y += ar * pi.y + ai * pi.x;
-    ri.x -= ar * qi.x - ai * qi.y;
-    ri.y -= ar * qi.y + ai * qi.x;
-    x[i] = xi;
-    r[i] = ri;
-    const R zr = di.x * ri.x - di.y * ri.y;
-    const R zi = di.x * ri.y + di.y * ri.x;
-    v[0] += (double)ri.x * zr - (double)ri.y * zi;
-    v[1] += (double)ri.x * zi + (double)ri.y * zr;
-    v[2] += (double)ri.x * ri.x + (double)ri.y * ri.y;
-    v[3] += (double)zr * zr + (double)zi * zi;
+  while (i0 < n) {
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t i = i0 + (int64_t)k * kBlock;
+      if (i >= n) continue;
+      const C pi = pv[k], qi = qv[k], di = dv[k];
+      C xi = xv[k], ri = rv[k];
+      xi.x += ar * pi.x - ai * pi.y;
+      xi.y += ar * pi.y + ai * pi.x;
+      ri.x -= ar * qi.x - ai * qi.y;
+      ri.y -= ar * qi.y + ai * qi.x;
+      x[i] = xi;
+      r[i] = ri;
+      const R zr = di.x * ri.x - di.y * ri.y;
+      const R zi = di.x * ri.y + di.y * ri.x;
+      v[0] += (double)ri.x * zr - (double)ri.y * zi;
+      v[1] += (double)ri.x * zi + (double)ri.y * zr;
+      v[2] += (double)ri.x * ri.x + (double)ri.y * ri.y;
+      v[3] += (double)zr * zr + (double)zi * zi;
+    }
+    i0 += stride;
+    if (i0 < n) load(i0);
   }
   store_partials4(v, pout);
 }
@@ -409,17 +458,36 @@ __global__ void __launch_bounds__(kBlock) k_cocg_pupdate(int64_t n, const typena
                                                          const double* __restrict__ pin, int nin, int par) {
   using C = typename Cx<R>::T;
   if (sc->done) return;
+  // operands of the first sweep and the scalars first (as in the update)
+  const int it = sc->iters[par] + 1;
+  const double rmax = sc->rr_max[par];
+  const double2 rho_old = sc->rho[par];
+  const double tol2bb = sc->tol2 * sc->bb, bd_tol = sc->bd_tol, delta2 = sc->delta2;
+  const int max_iters = sc->max_iters;
+  const int64_t stride = (int64_t)gridDim.x * kBlock * kPerThread;
+  int64_t i0 = (int64_t)blockIdx.x * kBlock * kPerThread + threadIdx.x;
+  C dv[kPerThread], rv[kPerThread], pv[kPerThread];
+  auto load = [&](int64_t b) {
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t i = b + (int64_t)k * kBlock;
+      if (i < n) {
+        dv[k] = dinv[i];
+        rv[k] = r[i];
+        pv[k] = p[i];
+      }
+    }
+  };
+  load(i0);
   double t[4];
   reduce_partials4(pin, nin, t);
   const double2 rho_new = make_double2(t[0], t[1]);
   const double rr = t[2], zz = t[3];
-  const int it = sc->iters[par] + 1;
-  const double rmax = sc->rr_max[par];
   int stop = 0;
-  if (rr <= sc->tol2 * sc->bb) stop = 1;
-  else if (it >= sc->max_iters) stop = 2;
-  else if (cabs2(rho_new) <= sc->bd_tol * sc->bd_tol * rr * zz) stop = 3;
-  else if (sc->delta2 > 0.0 && rr <= rmax && rr <= sc->delta2 * rmax) stop = 4;
+  if (rr <= tol2bb) stop = 1;
+  else if (it >= max_iters) stop = 2;
+  else if (cabs2(rho_new) <= bd_tol * bd_tol * rr * zz) stop = 3;
+  else if (delta2 > 0.0 && rr <= rmax && rr <= delta2 * rmax) stop = 4;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (stop) {
     // rho_{k-1} stays in slot par for the reliable update
@@ -432,7 +500,7 @@ __global__ void __launch_bounds__(kBlock) k_cocg_pupdate(int64_t n, const typena
     }
     return;
   }
-  const double2 beta = cdiv(rho_new, sc->rho[par]);
+  const double2 beta = cdiv(rho_new, rho_old);
   if (lead) {
     sc->rho[par ^ 1] = rho_new;
     sc->rr_max[par ^ 1] = rr > rmax ? rr : rmax;
@@ -442,17 +510,23 @@ __global__ void __launch_bounds__(kBlock) k_cocg_pupdate(int64_t n, const typena
     sc->beta = beta;
   }
   const R br = (R)beta.x, bi = (R)beta.y;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-    const C di = dinv[i], ri = r[i];
-    C pi = p[i];
-    const R zr = di.x * ri.x - di.y * ri.y;
-    const R zi = di.x * ri.y + di.y * ri.x;
-    const R nr = zr + br * pi.x - bi * pi.y;
-    const R ni = zi + br * pi.y + bi * pi.x;
-    pi.x = nr;
-    pi.y = ni;
-    p[i] = pi;
+  while (i0 < n) {
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t i = i0 + (int64_t)k * kBlock;
+      if (i >= n) continue;
+      const C di = dv[k], ri = rv[k];
+      C pi = pv[k];
+      const R zr = di.x * ri.x - di.y * ri.y;
+      const R zi = di.x * ri.y + di.y * ri.x;
+      const R nr = zr + br * pi.x - bi * pi.y;
+      const R ni = zi + br * pi.y + bi * pi.x;
+      pi.x = nr;
+      pi.y = ni;
+      p[i] = pi;
+    }
+    i0 += stride;
+    if (i0 < n) load(i0);
   }
 }
 
@@ -619,7 +693,7 @@ __global__ void __launch_bounds__(kBlock) k_norm2(int64_t n, const double2* __re
 namespace k {
 
 int reduce_blocks_for(int64_t n) {
-  int64_t b = (n + kBlock * 4 - 1) / (kBlock * 4);
+  int64_t b = (n + kBlock * kPerThread - 1) / (kBlock * kPerThread);
   if (b < 8) b = 8;
   if (b > 2048) b = 2048;
   return (int)((b + 7) / 8 * 8);
