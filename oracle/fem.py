@@ -25,6 +25,14 @@ What is computed (paper section 2, eqs. (1)-(4)), with the readings used:
       int_{S_ext} W . [ g(H_i) - n x curl H_i ] dS.
 * PEC elements are removed; PEC is a natural condition for H, so S_pec
   carries no term.  Faces not tagged ABC carry no term either.
+* Symmetry planes (section 3.1.3): an outer face tagged 2 is a symmetry
+  plane, n . H = 0 (eq. (6a)); one tagged 3 an antisymmetry plane,
+  n x H = 0 (eq. (6b)).  These are essential conditions: on every active
+  node of such a face the constrained components (the normal one, or the
+  two tangential ones) are fixed to zero by the usual elimination, their
+  rows and columns replaced by those of the identity and their right-hand
+  side entries by zero, which keeps the matrix complex-symmetric.  The
+  remaining components keep their natural conditions.
 * Quadrature: 2x2x2 Gauss points in volumes, 2x2 on faces; the incident
   field is evaluated exactly at the face Gauss points.
 
@@ -107,6 +115,44 @@ def element_matrices(h):
 
 # Outer faces: index f -> (normal axis, side); side 0 = minimum coordinate.
 FACES = [(0, 0), (0, 1), (1, 0), (1, 1), (2, 0), (2, 1)]
+
+# Outer-face tags: 0 ABC (eq. (3)), 1 natural (no term), 2 symmetry plane
+# n . H = 0 (eq. (6a)), 3 antisymmetry plane n x H = 0 (eq. (6b)).
+FACE_TAG_ABC, FACE_TAG_NATURAL, FACE_TAG_SYM, FACE_TAG_ANTISYM = 0, 1, 2, 3
+
+
+def constrained_unknowns(prob):
+    """Boolean mask (n_unknowns,) of the unknowns the symmetry planes fix to
+    zero (section 3.1.3): on every active node of a face tagged 2 the
+    component along the face normal (n . H = 0, eq. (6a)); on a face tagged
+    3 the two tangential components (n x H = 0, eq. (6b)).  A node on two
+    such faces collects both sets."""
+    mesh = Mesh(prob)
+    k, j, i = np.nonzero(mesh.node_active)
+    ijk = (i, j, k)
+    mask = np.zeros((mesh.n_nodes, 3), dtype=bool)
+    for f in range(6):
+        tag = prob.faces[f]
+        if tag not in (FACE_TAG_SYM, FACE_TAG_ANTISYM):
+            continue
+        axis, side = FACES[f]
+        n_axis = (mesh.nx, mesh.ny, mesh.nz)[axis]
+        on = ijk[axis] == (0 if side == 0 else n_axis)
+        comps = [axis] if tag == FACE_TAG_SYM else [c for c in range(3) if c != axis]
+        for c in comps:
+            mask[on, c] = True
+    return mask.ravel()
+
+
+def apply_constraints(A, constrained):
+    """Elimination of unknowns fixed to zero: their rows and columns become
+    those of the identity (P A P + I_c with P the projector on the free
+    unknowns)."""
+    if not constrained.any():
+        return A
+    free = sp.diags((~constrained).astype(np.float64))
+    fixed = sp.diags(constrained.astype(np.float64))
+    return (free @ A @ free + fixed).tocsr()
 
 
 def face_local_nodes(axis, side):
@@ -240,6 +286,8 @@ def assemble(prob, volume=True, abc=True):
         v = np.zeros(0, dtype=np.complex128)
     A = sp.coo_matrix((v, (r, c)), shape=(N, N)).tocsr()
     A.sum_duplicates()
+    A = apply_constraints(A, constrained_unknowns(prob))
+    A.sum_duplicates()
     return A
 
 
@@ -292,6 +340,7 @@ def rhs(prob, waves):
                         gradH = (-1j * k0) * Hi[:, c][:, None] * d_t[None, :]   # (F, 3)
                         term_s = (1j / (2.0 * k0)) * (gradH @ gt.T)              # (F, 4)
                         np.add.at(B[:, r], (3 * fnodes + c).ravel(), (w * (term_m + term_s)).ravel())
+    B[constrained_unknowns(prob), :] = 0.0
     return B
 
 
@@ -309,6 +358,7 @@ def assemble_rows(prob, nodes):
     k, j, i = np.nonzero(mesh.node_active)
     out = {}
     face_mats = {axis: face_matrices(axis, mesh.h) for axis in range(3)}
+    fixed = constrained_unknowns(prob).reshape(-1, 3)
     for node in nodes:
         node = int(node)
         gi, gj, gk = int(i[node]), int(j[node]), int(k[node])
@@ -346,6 +396,12 @@ def assemble_rows(prob, nodes):
                     for c in range(3):
                         if c != axis:
                             row[nb][c, c] += kf[pa, pb]
+        # symmetry-plane elimination: identity rows and columns
+        for nb, blk in row.items():
+            blk[fixed[node], :] = 0.0
+            blk[:, fixed[nb]] = 0.0
+            if nb == node:
+                blk[fixed[node], fixed[node]] = 1.0
         out[node] = row
     return out
 

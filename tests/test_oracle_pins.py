@@ -408,3 +408,71 @@ def test_row_sampler_matches_global_assembly():
         for b, blk in rows[a].items():
             got[:, 3 * b:3 * b + 3] = blk
         assert np.abs(got - full).max() <= 1e-14 * abs(A).max()
+
+
+# ------------------------------------------------------------ symmetry planes
+@pytest.mark.parametrize("cut_x,cut_y", [(True, False), (False, True), (True, True)])
+def test_symmetry_planes_reproduce_the_whole_box(cut_x, cut_y):
+    """Section 3.1.3: a mirror-symmetric box (PEC cube at the centre, x-polarised
+    wave along +z) solved on its x >= 0 half with n x H = 0 on x = 0 (eq. (6b)),
+    and/or its y >= 0 half with n . H = 0 on y = 0 (eq. (6a)), gives exactly the
+    whole box's nodal field there (direct solves on both).  Constraining the
+    wrong components, or dropping the elimination, breaks the equality."""
+    n = 8
+    full, waves = W.mirrored_pec_cube(n)
+    cut, _ = W.mirrored_pec_cube(n, cut_x=cut_x, cut_y=cut_y)
+    Hf = fem.scatter_to_grid(full, solve.sparse_solve(fem.assemble(full), fem.rhs(full, waves)))[0]
+    Hc = fem.scatter_to_grid(cut, solve.sparse_solve(fem.assemble(cut), fem.rhs(cut, waves)))[0]
+    x0 = n // 2 if cut_x else 0
+    y0 = n // 2 if cut_y else 0
+    ref = Hf[:, y0:, x0:, :]
+    scale = np.abs(Hf).max()
+    assert np.abs(Hc - ref).max() <= 1e-10 * scale
+    # the whole box's field obeys the plane conditions by itself
+    mid = n // 2
+    assert np.abs(Hf[:, :, mid, 1:]).max() <= 1e-10 * scale      # x = 0: H_y = H_z = 0
+    assert np.abs(Hf[:, mid, :, 1]).max() <= 1e-10 * scale       # y = 0: H_y = 0
+    assert np.abs(Hf[:, :, mid, 0]).max() > 1e-3 * scale         # H_x is free on x = 0
+
+
+def test_symmetry_plane_elimination_keeps_identity_rows():
+    """The fixed unknowns' rows and columns are those of the identity, their
+    right-hand side is zero, and the matrix stays complex-symmetric; an
+    antisymmetry face fixes the two tangential components and a symmetry
+    face the normal one."""
+    p, waves = W.mirrored_pec_cube(6, cut_x=True, cut_y=True)
+    A = fem.assemble(p).tocsr()
+    B = fem.rhs(p, waves)
+    C = fem.constrained_unknowns(p)
+    m = fem.Mesh(p)
+    k, j, i = np.nonzero(m.node_active)
+    on_x, on_y = i == 0, j == 0
+    expect = np.zeros((m.n_nodes, 3), bool)
+    expect[on_x, 1] = expect[on_x, 2] = True
+    expect[on_y, 1] = True
+    assert np.array_equal(C, expect.ravel())
+    idx = np.nonzero(C)[0]
+    sub = A[idx]
+    assert np.array_equal(sub.toarray(), np.eye(A.shape[0])[idx])
+    assert abs(A[:, idx] - sp_eye_cols(A.shape[0], idx)).max() == 0.0
+    assert np.all(B[idx] == 0)
+    assert abs(A - A.T).max() <= 1e-14 * abs(A).max()
+
+
+def sp_eye_cols(n, idx):
+    import scipy.sparse as sp
+    return sp.identity(n, dtype=np.complex128, format="csc")[:, idx]
+
+
+def test_row_sampler_applies_symmetry_planes():
+    """The one-row-at-a-time assembly applies the same elimination as the
+    global one."""
+    p, _ = W.mirrored_pec_cube(6, cut_x=True, cut_y=True)
+    A = fem.assemble(p).tocsr()
+    m = fem.Mesh(p)
+    nodes = np.arange(0, m.n_nodes, 7)
+    rows = fem.assemble_rows(p, nodes)
+    for a in nodes:
+        for b, blk in rows[int(a)].items():
+            ref = A[3 * int(a):3 * int(a) + 3, 3 * b:3 * b + 3].toarray()
+            assert np.allclose(blk, ref, rtol=0, atol=1e-13 * abs(A).max())

@@ -22,6 +22,8 @@ import numpy as np
 
 FACE_ABC = 0       # outer box face carries the absorbing boundary condition
 FACE_NATURAL = 1   # outer box face left with the natural condition (no surface term)
+FACE_SYM = 2       # symmetry plane, n . H = 0 (section 3.1.3, eq. (6a))
+FACE_ANTISYM = 3   # antisymmetry plane, n x H = 0 (section 3.1.3, eq. (6b))
 
 # Outer face order: -x, +x, -y, +y, -z, +z.
 FACE_NAMES = ("-x", "+x", "-y", "+y", "-z", "+z")
@@ -44,7 +46,7 @@ class Problem:
     eps_r: np.ndarray      # (nz, ny, nx) complex128, x fastest in memory
     mu_r: np.ndarray       # (nz, ny, nx) complex128
     pec: np.ndarray        # (nz, ny, nx) uint8, 1 = element removed (perfect conductor)
-    faces: Tuple[int, ...]  # 6 face tags (FACE_ABC / FACE_NATURAL)
+    faces: Tuple[int, ...]  # 6 face tags (FACE_ABC / FACE_NATURAL / FACE_SYM / FACE_ANTISYM)
     k0: float
     penalty_s: float = 1.0
     name: str = ""
@@ -168,6 +170,42 @@ class Request:
     arrival_s: float
     problem: Problem
     waves: List[PlaneWave]
+
+
+def mirrored_pec_cube(n: int = 12, side: float = 0.4, cut_x: bool = False,
+                      cut_y: bool = False) -> Tuple[Problem, List[PlaneWave]]:
+    """Box of n^3 elements (n even, h = 0.1) centred on the origin around a
+    centred PEC cube of the given side, ABC on the outer faces, lit by the
+    x-polarised wave travelling along +z.  The problem is mirror-symmetric in
+    x and in y, and so is this incident field: H is even under x -> -x
+    (H_x even, H_y and H_z odd), so n x H = 0 on the plane x = 0, and odd
+    under y -> -y (H_y odd), so n . H = 0 on y = 0.  cut_x keeps the half
+    x >= 0 with its -x face tagged FACE_ANTISYM; cut_y keeps y >= 0 with its
+    -y face tagged FACE_SYM.  The cut problem's nodal solution equals the
+    whole box's restricted to the kept part."""
+    if n % 2:
+        raise ValueError("n must be even")
+    h = 0.1
+    half = n // 2
+    full = _blank(n, n, n, (h, h, h), (-half * h, -half * h, -half * h), 2.0 * math.pi,
+                  name=f"mirrored_pec_cube_{n}")
+    s = side / 2.0
+    full.pec = box_mask(full, (-s, -s, -s), (s, s, s)).astype(np.uint8)
+    x0 = half if cut_x else 0
+    y0 = half if cut_y else 0
+    faces = list(full.faces)
+    if cut_x:
+        faces[0] = FACE_ANTISYM
+    if cut_y:
+        faces[2] = FACE_SYM
+    p = dataclasses.replace(
+        full, nx=n - x0, ny=n - y0,
+        origin=(full.origin[0] + x0 * h, full.origin[1] + y0 * h, full.origin[2]),
+        eps_r=np.ascontiguousarray(full.eps_r[:, y0:, x0:]), mu_r=np.ascontiguousarray(full.mu_r[:, y0:, x0:]),
+        pec=np.ascontiguousarray(full.pec[:, y0:, x0:]), faces=tuple(faces),
+        name=full.name + ("_x" if cut_x else "") + ("_y" if cut_y else ""))
+    w = PlaneWave(d=np.array([0.0, 0.0, 1.0]), p=np.array([1.0, 0.0, 0.0], np.complex128))
+    return p, [w]
 
 
 def serving_request(rng: np.random.Generator, n_lo: int = 10, n_hi: int = 100,
