@@ -66,9 +66,17 @@ typedef enum {
   FEMH_E_NOT_FOUND = -9       /* unknown server ticket */
 } femh_status;
 
-/* Outer face tags, faces ordered -x, +x, -y, +y, -z, +z. */
+/* Outer face tags, faces ordered -x, +x, -y, +y, -z, +z.  The two plane
+ * conditions of section 3.1.3 are essential: on every active node of the
+ * face the constrained components are fixed to zero by elimination (their
+ * matrix rows and columns are those of the identity, their right-hand side
+ * entries zero, so the matrix stays complex-symmetric); the other
+ * components keep the natural condition.  A node on two such faces
+ * collects both constraints. */
 enum { FEMH_FACE_ABC = 0,      /* eq. (3) absorbing condition */
-       FEMH_FACE_NATURAL = 1   /* no surface term (a PEC wall for H) */ };
+       FEMH_FACE_NATURAL = 1,  /* no surface term (a PEC wall for H) */
+       FEMH_FACE_SYM = 2,      /* symmetry plane, n . H = 0 (eq. (6a)): the normal component fixed */
+       FEMH_FACE_ANTISYM = 3   /* antisymmetry plane, n x H = 0 (eq. (6b)): the tangential ones fixed */ };
 
 typedef enum { FEMH_FP64 = 0,          /* complex128 matrix and Krylov vectors */
                FEMH_MIXED = 1,         /* complex64 matrix and Krylov vectors (FP32 arithmetic),

@@ -45,6 +45,8 @@ struct MeshDev {
   double h[3], origin[3];
   double k0, s;
   int abc_mask;              // bit f set = outer face f carries the ABC
+  int sym_mask;              // bit f set = outer face f is a symmetry plane (n . H = 0)
+  int anti_mask;             // bit f set = outer face f is an antisymmetry plane (n x H = 0)
   const double2* eps;        // [ne] or null (= 1)
   const double2* mu;         // [ne] or null (= 1)
   const uint8_t* pec;        // [ne] or null (= none)

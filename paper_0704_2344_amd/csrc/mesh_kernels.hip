@@ -171,6 +171,25 @@ __device__ __forceinline__ double m1(int a, int b, double h) { return h * (a == 
 __device__ __forceinline__ double k1(int a, int b, double h) { return (a == b ? 1.0 : -1.0) / h; }
 __device__ __forceinline__ double g1(int a) { return a ? 0.5 : -0.5; }
 
+// Components of the node at grid index gi fixed to zero by the plane faces
+// (section 3.1.3): bit c set = component c.  A symmetry face fixes the
+// component along its normal (n . H = 0), an antisymmetry face the two
+// tangential ones (n x H = 0).
+__device__ __forceinline__ int fixed_components(const MeshDev& m, const int (&gi)[3]) {
+  const int planes = m.sym_mask | m.anti_mask;
+  if (!planes) return 0;
+  const int nel[3] = {m.nx, m.ny, m.nz};
+  int cm = 0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    if (!((planes >> f) & 1)) continue;
+    const int ax = f >> 1, side = f & 1;
+    if (gi[ax] != (side ? nel[ax] : 0)) continue;
+    cm |= ((m.sym_mask >> f) & 1) ? (1 << ax) : (7 & ~(1 << ax));
+  }
+  return cm;
+}
+
 __global__ void __launch_bounds__(256) k_assemble(MeshDev m, PatternDev p, int32_t* __restrict__ col_idx,
                                                   double2* __restrict__ val64, float2* __restrict__ val32,
                                                   double2* __restrict__ dinv64, float2* __restrict__ dinv32) {
@@ -273,6 +292,20 @@ __global__ void __launch_bounds__(256) k_assemble(MeshDev m, PatternDev p, int32
           }
         }
       }
+  // plane conditions: the fixed components' rows and columns become those of
+  // the identity (slot 13 is the diagonal block)
+  {
+    const int gb3[3] = {gi[0] + d[0], gi[1] + d[1], gi[2] + d[2]};
+    const int ca = fixed_components(m, gi), cb = fixed_components(m, gb3);
+    if (ca | cb) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          if (((ca >> i) & 1) || ((cb >> j) & 1))
+            K[i][j] = make_double2(slot == 13 && i == j ? 1.0 : 0.0, 0.0);
+    }
+  }
   double2* o64 = val64 + pos * 9;
   float2* o32 = val32 + pos * 9;
 #pragma unroll
@@ -366,6 +399,10 @@ __global__ void k_rhs(MeshDev m, PatternDev p, int32_t nrhs, const femh_plane_wa
       }
     }
   }
+  const int ca = fixed_components(m, gi);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if ((ca >> c) & 1) acc[c] = make_double2(0.0, 0.0);
   double2* out = b + (int64_t)r * 3 * p.nn + 3 * (int64_t)a;
   out[0] = acc[0];
   out[1] = acc[1];

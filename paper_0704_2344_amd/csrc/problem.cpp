@@ -98,8 +98,8 @@ int validate_desc(const femh_problem_desc* d, std::string& msg) {
     return FEMH_E_INVALID;
   }
   for (int f = 0; f < 6; ++f)
-    if (d->outer_face[f] != FEMH_FACE_ABC && d->outer_face[f] != FEMH_FACE_NATURAL) {
-      msg = "outer_face entries must be FEMH_FACE_ABC or FEMH_FACE_NATURAL";
+    if (d->outer_face[f] < FEMH_FACE_ABC || d->outer_face[f] > FEMH_FACE_ANTISYM) {
+      msg = "outer_face entries must be FEMH_FACE_ABC, _NATURAL, _SYM or _ANTISYM";
       return FEMH_E_INVALID;
     }
   if (d->arrays_on_device != 0 && d->arrays_on_device != 1) {
@@ -248,9 +248,12 @@ static void fill_mesh(MeshDev& m, const femh_problem_desc* d) {
   }
   m.k0 = d->k0;
   m.s = d->penalty_s == 0.0 ? 1.0 : d->penalty_s;
-  m.abc_mask = 0;
-  for (int f = 0; f < 6; ++f)
+  m.abc_mask = m.sym_mask = m.anti_mask = 0;
+  for (int f = 0; f < 6; ++f) {
     if (d->outer_face[f] == FEMH_FACE_ABC) m.abc_mask |= 1 << f;
+    if (d->outer_face[f] == FEMH_FACE_SYM) m.sym_mask |= 1 << f;
+    if (d->outer_face[f] == FEMH_FACE_ANTISYM) m.anti_mask |= 1 << f;
+  }
   m.eps = nullptr;
   m.mu = nullptr;
   m.pec = nullptr;

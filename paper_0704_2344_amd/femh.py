@@ -35,6 +35,8 @@ STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NONFINITE", -3: "OOM", -4: "DEVICE"
 
 FEMH_FACE_ABC = 0
 FEMH_FACE_NATURAL = 1
+FEMH_FACE_SYM = 2
+FEMH_FACE_ANTISYM = 3
 FEMH_FP64 = 0
 FEMH_MIXED = 1
 FEMH_MIXED_MATRIX = 2

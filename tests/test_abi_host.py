@@ -71,6 +71,17 @@ def test_validation_accepts_workloads(lib):
         assert lib.femh_validate_waves(len(waves), w, buf, 256) == F.FEMH_OK
 
 
+def test_validation_accepts_plane_faces(lib):
+    """Symmetry (2) and antisymmetry (3) plane tags are valid outer faces."""
+    for cut_x, cut_y in ((True, False), (False, True), (True, True)):
+        p, _ = W.mirrored_pec_cube(6, cut_x=cut_x, cut_y=cut_y)
+        st, msg = _validate(lib, p)
+        assert st == F.FEMH_OK, msg
+    p, _ = W.free_cube(3)
+    p.faces = (F.FEMH_FACE_SYM, F.FEMH_FACE_ANTISYM, F.FEMH_FACE_NATURAL, F.FEMH_FACE_ABC, 2, 3)
+    assert _validate(lib, p)[0] == F.FEMH_OK
+
+
 def test_validation_rejects_bad_descriptors(lib):
     p, _ = W.free_cube(3)
     bad = []
@@ -96,6 +107,12 @@ def test_validation_rejects_bad_descriptors(lib):
     bad.append((q, F.FEMH_E_INVALID))
     q, _ = W.free_cube(3)
     q.faces = (0, 0, 7, 0, 0, 0)
+    bad.append((q, F.FEMH_E_INVALID))
+    q, _ = W.free_cube(3)
+    q.faces = (0, 0, 4, 0, 0, 0)
+    bad.append((q, F.FEMH_E_INVALID))
+    q, _ = W.free_cube(3)
+    q.faces = (0, -1, 0, 0, 0, 0)
     bad.append((q, F.FEMH_E_INVALID))
     q, _ = W.free_cube(3)
     q.penalty_s = -1.0

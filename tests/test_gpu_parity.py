@@ -58,6 +58,10 @@ def small_cases():
     cases["thin_slab"] = (p, [W.random_wave(rng)])
     p, waves = W.pec_sphere_shell(n=14, radius=0.3, shell=0.12, seed=3)
     cases["sphere_shell_14"] = (p, waves)
+    # symmetry-plane faces (section 3.1.3): antisymmetry plane on -x, and
+    # both an antisymmetry (-x) and a symmetry (-y) plane
+    cases["mirror_cut_x"] = W.mirrored_pec_cube(8, cut_x=True)
+    cases["mirror_cut_xy"] = W.mirrored_pec_cube(8, cut_x=True, cut_y=True)
     return cases
 
 
@@ -144,7 +148,7 @@ def _lu_solution(prob, waves):
 
 
 @pytest.mark.parametrize("name", ["free_cube_10", "random_pec_lossy", "aniso_partial_abc", "one_element",
-                                  "thin_slab"])
+                                  "thin_slab", "mirror_cut_x", "mirror_cut_xy"])
 def test_fp64_solve_matches_lu(ctx, name):
     prob, waves = CASES[name]
     A, B, X = _lu_solution(prob, waves)
@@ -168,7 +172,7 @@ def test_fp64_solve_matches_lu(ctx, name):
 
 
 @pytest.mark.parametrize("prec", [F.FEMH_MIXED, F.FEMH_MIXED_MATRIX])
-@pytest.mark.parametrize("name", ["free_cube_10", "random_pec_lossy", "sphere_shell_14"])
+@pytest.mark.parametrize("name", ["free_cube_10", "random_pec_lossy", "sphere_shell_14", "mirror_cut_xy"])
 def test_mixed_solve_matches_lu(ctx, name, prec):
     prob, waves = CASES[name]
     A, B, X = _lu_solution(prob, waves)
@@ -181,6 +185,46 @@ def test_mixed_solve_matches_lu(ctx, name, prec):
         assert err <= 1e-6, (r, err, stats[r])
         assert stats[r]["outer_iters"] >= 1
     P.close()
+
+
+@pytest.mark.parametrize("cut_x,cut_y", [(True, False), (False, True), (True, True)])
+def test_plane_faces_reproduce_the_whole_box(ctx, cut_x, cut_y):
+    """The GPU solve of the x >= 0 / y >= 0 part of the mirror-symmetric box
+    with its cut face(s) tagged as (anti)symmetry planes equals the oracle's
+    direct solve of the whole box there (forward error 1e-9)."""
+    n = 8
+    full, waves = W.mirrored_pec_cube(n)
+    cut, _ = W.mirrored_pec_cube(n, cut_x=cut_x, cut_y=cut_y)
+    A, B, X = _lu_solution(full, waves)
+    ref = fem.scatter_to_grid(full, X)[0][:, n // 2 if cut_y else 0:, n // 2 if cut_x else 0:, :]
+    Ac = fem.assemble(cut)
+    kappa = float(abs(np.linalg.cond(Ac.toarray(), 1)))
+    P = F.Problem(ctx, cut)
+    H, stats, st = P.solve(waves, precision=F.FEMH_FP64, rtol=min(1e-10, 0.1 * 1e-9 / kappa))
+    assert st == F.FEMH_OK, stats
+    assert np.linalg.norm(H[0] - ref) / np.linalg.norm(ref) <= 1e-9
+    P.close()
+
+
+def test_plane_faces_full_size_quarter(ctx):
+    """30^3 mirror-symmetric box against its quarter (15 x 15 x 30 elements,
+    antisymmetry plane on -x, symmetry plane on -y), both solved on the GPU in
+    FP64 to 1e-10: the quarter's field equals the whole box's there to the
+    solves' accuracy, with a quarter of the unknowns."""
+    n = 30
+    full, waves = W.mirrored_pec_cube(n, side=1.0)
+    cut, _ = W.mirrored_pec_cube(n, side=1.0, cut_x=True, cut_y=True)
+    Pf = F.Problem(ctx, full)
+    Hf, sf, st = Pf.solve(waves, precision=F.FEMH_FP64, rtol=1e-10)
+    assert st == F.FEMH_OK, sf
+    Pc = F.Problem(ctx, cut)
+    assert Pc.n_unknowns < 0.3 * Pf.n_unknowns
+    Hc, sc, st = Pc.solve(waves, precision=F.FEMH_FP64, rtol=1e-10)
+    assert st == F.FEMH_OK, sc
+    ref = Hf[0][:, n // 2:, n // 2:, :]
+    assert np.linalg.norm(Hc[0] - ref) / np.linalg.norm(ref) <= 1e-6, (sf, sc)
+    Pf.close()
+    Pc.close()
 
 
 def test_solve_is_deterministic(ctx):
