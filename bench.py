@@ -20,6 +20,9 @@ Also printed on the same JSON line:
                 FP64 batched solve to 1e-6 (RHS/s, SpMM time, GB/s and
                 TFLOP/s), against single-RHS FP64 and matrix-mixed solves of
                 the same waves
+  planes        the mirror-symmetric 30^3 PEC-cube box solved whole and as
+                its quarter with an antisymmetry and a symmetry plane (FP64
+                to 1e-8): solves/s of each and the quarter's deviation
   serving       a Poisson stream of scattering requests (meshes n^3 with n in
                 [10, serve_n_hi], 1-4 waves each) through the continuous-
                 batching server in matrix-mixed and FP64 precision, and the
@@ -178,8 +181,8 @@ def main():
     ap.add_argument("--cmp-steps", type=int, default=3, help="steps per solver in the 1e-6 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip every leg but the headline")
-    ap.add_argument("--extras", default="cmp,hbm,batched,serving",
-                    help="legs after the headline, comma-separated subset of cmp,hbm,batched,serving")
+    ap.add_argument("--extras", default="cmp,hbm,batched,planes,serving",
+                    help="legs after the headline, comma-separated subset of cmp,hbm,batched,planes,serving")
     ap.add_argument("--batched-singles", type=int, default=4,
                     help="single-RHS solves per precision timed beside the batched leg (0 skips them)")
     ap.add_argument("--cpu-sample-iters", type=int, default=300)
@@ -278,7 +281,7 @@ def main():
         result["copy_probe_GBps"] = ctx.bw_probe(1 << 30, 3)
 
     legs = set() if args.no_extras else {x for x in args.extras.split(",") if x}
-    unknown = legs - {"cmp", "hbm", "batched", "serving"}
+    unknown = legs - {"cmp", "hbm", "batched", "planes", "serving"}
     if unknown:
         raise SystemExit(f"unknown --extras legs: {sorted(unknown)}")
 
@@ -361,6 +364,36 @@ def main():
                              "single_rhs_fp64_rhs_per_s": 1.0 / single["fp64"] if single["fp64"] else None,
                              "speedup_vs_single_fp64": (64 / el3) * single["fp64"] if single["fp64"] else None}
         P3.close()
+
+    if "planes" in legs:
+        # symmetry planes: the mirror-symmetric 30^3 box against its quarter
+        # (antisymmetry plane on -x, symmetry plane on -y)
+        n4 = 30
+        legs_out = {}
+        fields = {}
+        for name, cx in (("whole", False), ("quarter", True)):
+            p4, w4 = W.mirrored_pec_cube(n4, side=1.0, cut_x=cx, cut_y=cx)
+            o4 = torch.zeros((1, p4.nz + 1, p4.ny + 1, p4.nx + 1, 3), dtype=torch.complex128, device=dev)
+            P4 = F.Problem(ctx, p4)
+            P4.solve_dev(w4, o4, precision=F.FEMH_FP64, rtol=1e-8)        # warm-up
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            reps4 = 3
+            for _ in range(reps4):
+                s4, st4 = P4.solve_dev(w4, o4, precision=F.FEMH_FP64, rtol=1e-8)
+            torch.cuda.synchronize()
+            t4 = (time.perf_counter() - a) / reps4
+            legs_out[name] = {"status": st4, "n_unknowns": P4.n_unknowns, "iters": s4[0]["iters"],
+                              "solve_s": t4, "solves_per_s": 1.0 / t4}
+            fields[name] = o4[0].cpu().numpy()
+            P4.close()
+        ref = fields["whole"][:, n4 // 2:, n4 // 2:, :]
+        legs_out["quarter_vs_whole_rel_l2"] = float(np.linalg.norm(fields["quarter"] - ref) / np.linalg.norm(ref))
+        legs_out["speedup"] = legs_out["quarter"]["solves_per_s"] / legs_out["whole"]["solves_per_s"]
+        legs_out["workload"] = ("mirrored_pec_cube_30: 30^3 box centred on a PEC cube of one wavelength, x-polarised "
+                                "wave along +z, FP64 to 1e-8; the quarter x >= 0, y >= 0 with n x H = 0 on x = 0 "
+                                "and n . H = 0 on y = 0")
+        result["planes"] = legs_out
 
     if "serving" in legs and args.serve_requests > 0:
         result["serving"] = serving_leg(ctx, F, W, args.serve_requests, args.serve_rate, args.serve_n_hi)
