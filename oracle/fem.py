@@ -291,6 +291,62 @@ def assemble(prob, volume=True, abc=True):
     return A
 
 
+def penalty_surface_matrix(prob):
+    """The penalty's surface integral as eq. (4) prints it (from eq. (2)),
+    which the main reading drops.  In the standard operator sign used here
+    it is  -s int_{S_ext + S_pec} (W . n)(div H) dS,  with S_ext the outer
+    faces tagged ABC, S_pec the faces between an active and a PEC element,
+    and n the outward normal of the active region; entry (3a + i, 3b + j) of
+    one element face is  -s n_i int N_a dN_b/dx_j dS  (2x2 Gauss).  Not
+    symmetric: the paper averages the system matrix with its transpose
+    (section 3.1.4).  An oracle option, used to quantify that reading."""
+    mesh = Mesh(prob)
+    h = mesh.h
+    s = prob.penalty_s
+    pec = np.asarray(prob.pec).reshape(mesh.nz, mesh.ny, mesh.nx)
+    n_el = (mesh.nx, mesh.ny, mesh.nz)
+    rows, cols, vals = [], [], []
+    dofs = _element_dofs(mesh)
+    for f in range(6):
+        axis, side = FACES[f]
+        sgn = 1.0 if side else -1.0
+        tang = [t for t in range(3) if t != axis]
+        area = h[tang[0]] * h[tang[1]]
+        F = np.zeros((24, 24))
+        for w1, p1 in zip(GAUSS_WEIGHTS_UNIT, GAUSS_POINTS_UNIT):
+            for w2, p2 in zip(GAUSS_WEIGHTS_UNIT, GAUSS_POINTS_UNIT):
+                xi = np.zeros(3)
+                xi[axis] = float(side)
+                xi[tang[0]], xi[tang[1]] = p1, p2
+                N, dN = volume_basis_at(xi, h)
+                for a in range(8):
+                    for b in range(8):
+                        F[3 * a + axis, 3 * b:3 * b + 3] += -s * sgn * w1 * w2 * area * N[a] * dN[b]
+        ijk = mesh.elem_ijk
+        nb = ijk.copy()
+        nb[:, axis] += 1 if side else -1
+        outside = (nb[:, axis] < 0) | (nb[:, axis] >= n_el[axis])
+        sel = outside & (prob.faces[f] == 0)
+        inside = ~outside
+        pec_nb = np.zeros(len(ijk), dtype=bool)
+        pec_nb[inside] = pec[nb[inside, 2], nb[inside, 1], nb[inside, 0]] != 0
+        sel |= pec_nb
+        idx = np.nonzero(sel)[0]
+        if len(idx) == 0:
+            continue
+        d = dofs[idx]
+        rows.append(np.broadcast_to(d[:, :, None], (len(idx), 24, 24)).ravel())
+        cols.append(np.broadcast_to(d[:, None, :], (len(idx), 24, 24)).ravel())
+        vals.append(np.broadcast_to(F[None], (len(idx), 24, 24)).ravel())
+    N = mesh.n_unknowns
+    if not rows:
+        return sp.csr_matrix((N, N), dtype=np.complex128)
+    S = sp.coo_matrix((np.concatenate(vals).astype(np.complex128),
+                       (np.concatenate(rows), np.concatenate(cols))), shape=(N, N)).tocsr()
+    S.sum_duplicates()
+    return S
+
+
 def incident_field(wave, pts, k0):
     """H_i = p exp(-j k0 d.r) at points (m, 3) -> (m, 3) complex."""
     ph = np.exp(-1j * k0 * (pts @ np.asarray(wave.d, dtype=np.float64)))

@@ -476,3 +476,56 @@ def test_row_sampler_applies_symmetry_planes():
         for b, blk in rows[int(a)].items():
             ref = A[3 * int(a):3 * int(a) + 3, 3 * b:3 * b + 3].toarray()
             assert np.allclose(blk, ref, rtol=0, atol=1e-13 * abs(A).max())
+
+
+# ---------------------------------------- the printed penalty surface term
+def test_penalty_surface_term_closed_form():
+    """The literal surface term -s int (W.n)(div H) dS applied to the nodal
+    interpolant of a constant field is zero (div H = 0).  Applied to
+    H = (x, 0, 0) (div H = 1) it gives -s n_k int N_a dS in row (a, k), so
+    the k rows summed over the nodes of the face normal to axis k on side
+    +/- give -/+ s times that face's area (partition of unity), and the k
+    rows of nodes on neither of those two faces are zero."""
+    p, _ = W.free_cube(4)
+    p.h = (0.1, 0.15, 0.2)
+    p.penalty_s = 0.7
+    S = fem.penalty_surface_matrix(p)
+    m = fem.Mesh(p)
+    xyz = m.node_coords()
+    const = np.tile(np.array([1.0, -2.0, 0.5]), m.n_nodes)
+    assert np.abs(S @ const).max() <= 1e-13
+    hx = np.zeros((m.n_nodes, 3))
+    hx[:, 0] = xyz[:, 0]
+    y = (S @ hx.ravel()).reshape(-1, 3)
+    ext = np.array([p.nx * p.h[0], p.ny * p.h[1], p.nz * p.h[2]])
+    for k in range(3):
+        t = [a for a in range(3) if a != k]
+        area = ext[t[0]] * ext[t[1]]
+        on_plus = np.isclose(xyz[:, k], ext[k])
+        on_minus = np.isclose(xyz[:, k], 0.0)
+        assert abs(y[on_plus, k].sum() - (-p.penalty_s * area)) <= 1e-12
+        assert abs(y[on_minus, k].sum() - (+p.penalty_s * area)) <= 1e-12
+        assert np.abs(y[~(on_plus | on_minus), k]).max() <= 1e-13
+
+
+def test_printed_penalty_term_with_symmetrisation_breaks_the_empty_box():
+    """Reading A3 (surface term dropped, matrix symmetric) reproduces the
+    incident wave in an empty ABC box to discretisation error; keeping the
+    printed surface term does too (it vanishes on divergence-free fields);
+    but averaging that matrix with its transpose, as section 3.1.4 does, adds
+    -s int (div W)(H.n) dS, which does not vanish on H_i, and the solution no
+    longer resembles it (measured: 4.8 %, 6.4 % and 90 % at 10^3)."""
+    p, waves = W.free_cube(10)
+    A = fem.assemble(p)
+    b = fem.rhs(p, waves)[:, 0]
+    S = fem.penalty_surface_matrix(p)
+    Hi = fem.incident_field(waves[0], fem.Mesh(p).node_coords(), p.k0).ravel()
+
+    def err(M):
+        x = solve.sparse_solve(M.tocsc(), b)
+        return np.linalg.norm(x - Hi) / np.linalg.norm(Hi)
+
+    e_a3, e_lit = err(A), err(A + S)
+    e_sym = err(((A + S) + (A + S).T) / 2)
+    assert e_a3 < 0.06 and e_lit < 0.1
+    assert e_sym > 0.5
