@@ -314,6 +314,11 @@ def main():
             t = P2.spmv_dev(xx, yy, prec, reps=20)
             gb = spmv_bytes(P2.n_nodes, P2.nnzb, vb, xb) / t / 1e9
             hb[name] = {"us": t * 1e6, "GBps": gb, "frac_hbm_peak": gb / HBM_PEAK_GBPS}
+        # the symmetric half store (storage #1 analogue): same product, about
+        # half the stored blocks
+        t_half = P2.spmv_half_dev(x, y, reps=3)
+        t_half = P2.spmv_half_dev(x, y, reps=10)
+        hb["c128_half_store"] = {"us": t_half * 1e6, "vs_full_store": hb["c128"]["us"] / (t_half * 1e6)}
         hb["workload"] = f"pec_sphere_shell_60 matrix: {n2} unknowns, {P2.nnzb} blocks"
         hb["copy_probe_GBps"] = ctx.bw_probe(1 << 30, 10)
         result["spmv_hbm"] = hb

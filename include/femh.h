@@ -259,6 +259,15 @@ int femh_spmv_dev(femh_problem* prob, int32_t precision, const void* x_dev, void
 int femh_spmm_dev(femh_problem* prob, int32_t precision, int32_t ncols, const void* X_dev, void* Y_dev,
                   int32_t reps, double* avg_seconds);
 
+/* y = A x (complex128) from the symmetric half store: the matrix is
+ * complex-symmetric block by block (A_ba = A_ab^T), so each block row keeps
+ * only its blocks with column <= row (the analogue of the paper's storage
+ * #1, section 4.2) and reads the others transposed from the rows that store
+ * them.  The store (about 52 % of the blocks plus an int32 per block) is
+ * built on the first call and kept with the problem.  Timing as
+ * femh_spmv_dev. */
+int femh_spmv_half_dev(femh_problem* prob, const void* x_dev, void* y_dev, int32_t reps, double* avg_seconds);
+
 /* The wide SpMM shape the batched solver uses for this problem: *kind = 0
  * FP64 vector FMAs (the only kind the autotuner times, over grid sizes, on
  * the problem's first wide product, with that product's matrix), 1

@@ -466,6 +466,31 @@ int femh_spmv_dev(femh_problem* p, int32_t precision, const void* x, void* y, in
   return FEMH_OK;
 }
 
+int femh_spmv_half_dev(femh_problem* p, const void* x, void* y, int32_t reps, double* avg_seconds) {
+  femh::clear_error();
+  if (!p || !x || !y || reps < 1) {
+    femh::set_error("bad spmv arguments");
+    return FEMH_E_INVALID;
+  }
+  FEMH_TRY(femh::ensure_half_store(p));
+  Ctx* c = p->ctx;
+  hipEvent_t e0, e1;
+  FEMH_TRY_HIP(hipEventCreate(&e0));
+  FEMH_TRY_HIP(hipEventCreate(&e1));
+  FEMH_TRY_HIP(hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i)
+    FEMH_TRY_HIP(femh::k::spmv_half_c128(c->stream, p->pat, p->hval64, p->hpos, (const double2*)x, (double2*)y,
+                                         p->spmv));
+  FEMH_TRY_HIP(hipEventRecord(e1, c->stream));
+  FEMH_TRY_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  FEMH_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+  if (avg_seconds) *avg_seconds = ms * 1e-3 / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return FEMH_OK;
+}
+
 int femh_bw_probe(femh_ctx* c, int64_t bytes, int32_t reps, double* gbps) {
   femh::clear_error();
   if (!c || bytes < 16 || reps < 1 || !gbps) {

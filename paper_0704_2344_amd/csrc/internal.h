@@ -180,6 +180,11 @@ struct SpmvLaunch {
 };
 SpmvLaunch spmv_launch_for(int32_t nn, int n_cu);
 
+// Symmetric half store: hpos[nnzb] per block slot (stored index, or
+// -(index + 1) for the transpose of a stored block), hval[stored][9].
+hipError_t spmv_half_c128(hipStream_t st, const PatternDev& p, const double2* hval, const int32_t* hpos,
+                          const double2* x, double2* y, SpmvLaunch L);
+hipError_t gather_half(hipStream_t st, int64_t nnzb, const int32_t* hpos, const double2* val, double2* hval);
 hipError_t spmv_c128(hipStream_t st, const PatternDev& p, const double2* val, const double2* x,
                      double2* y, SpmvLaunch L);
 hipError_t spmv_c64(hipStream_t st, const PatternDev& p, const float2* val, const float2* x,
@@ -298,6 +303,9 @@ struct Problem {
   k::SpmvLaunch spmv{};
   BatchTile tile{-1, 0};  // autotuned SpMM shape (kind -1 = not tuned yet)
   int32_t* row_order = nullptr;  // wide SpMM traversal order (device, [nn])
+  int32_t* hpos = nullptr;        // symmetric half store: per block slot index (device, [nnzb])
+  double2* hval64 = nullptr;      // symmetric half store values (device, [stored][9])
+  int64_t n_half = 0;             // stored blocks
 
   std::vector<void*> owned;
   void* alloc(size_t bytes);  // tracked allocation, freed with the problem
@@ -329,6 +337,8 @@ int autotune_spmm(Problem* P, const double2* val64, const double2* Pv, double2* 
                   const BatchScalars* sc);
 // Builds P->row_order (and P->pat.row_order) once per problem.
 int ensure_row_order(Problem* P);
+// Builds the symmetric half store (P->hpos, P->hval64) once per problem.
+int ensure_half_store(Problem* P);
 
 // Single-RHS solve as a non-blocking state machine (one code path for
 // femh_solve and the server).  step() queues the work its phase allows and

@@ -64,10 +64,14 @@ __device__ __forceinline__ R shfl_down_z(R v, int off, int lane) {
 // rows[] are wave-uniform; rows >= nn contribute nothing.
 // VC is the stored value type (complex64 values are promoted to R in the
 // product when the vectors are complex128).
-template <typename R, int NR, typename VC = typename Cx<R>::T>
+// With kHalf the values are the symmetric half store: hpos[k] of block slot
+// k is the stored block's index, or -(index + 1) when the slot's block is
+// the transpose of a stored one (its entry (i, j) is stored entry (j, i)).
+template <typename R, int NR, typename VC = typename Cx<R>::T, bool kHalf = false>
 __device__ __forceinline__ void rows_product(const PatternDev& p, const VC* __restrict__ val,
                                              const typename Cx<R>::T* __restrict__ x, const int32_t (&rows)[NR],
-                                             int lane, R (&yr)[NR], R (&yi)[NR]) {
+                                             int lane, R (&yr)[NR], R (&yi)[NR],
+                                             const int32_t* __restrict__ hpos = nullptr) {
   using C = typename Cx<R>::T;
   const int e = lane % 9;
   const int bo = lane / 9;
@@ -92,7 +96,14 @@ __device__ __forceinline__ void rows_product(const PatternDev& p, const VC* __re
     for (int kk = 0; kk < 4; ++kk) {
       const int b = bo + 7 * kk;
       if (b < nb[k]) {
-        a[k][kk] = ld_stream(val + (size_t)(beg[k] + b) * 9 + e);
+        if (kHalf) {
+          const int32_t hp = hpos[beg[k] + b];
+          const bool tr = hp < 0;
+          const size_t q = tr ? (size_t)(-(hp + 1)) : (size_t)hp;
+          a[k][kk] = ld_stream(val + q * 9 + (tr ? 3 * (e % 3) + e / 3 : e));
+        } else {
+          a[k][kk] = ld_stream(val + (size_t)(beg[k] + b) * 9 + e);
+        }
         c[k][kk] = p.col_idx[beg[k] + b];
       }
     }
@@ -142,6 +153,40 @@ __device__ __forceinline__ int wave_row_start(int& nwaves) {
 }
 
 constexpr int kRowsPerWave = 1;  // rows a wave keeps in flight (2 costs occupancy: measured slower)
+
+// y = A x from the symmetric half store (see rows_product).
+template <typename R, typename VC = typename Cx<R>::T>
+__global__ void __launch_bounds__(kBlock) k_spmv_half(PatternDev p, const VC* __restrict__ hval,
+                                                      const int32_t* __restrict__ hpos,
+                                                      const typename Cx<R>::T* __restrict__ x,
+                                                      typename Cx<R>::T* __restrict__ y) {
+  using C = typename Cx<R>::T;
+  const int lane = threadIdx.x & 63;
+  int nwaves;
+  const int w = wave_row_start(nwaves);
+  for (int32_t r0 = w; r0 < p.nn; r0 += nwaves) {
+    int32_t rows[1] = {r0};
+    R yr[1], yi[1];
+    rows_product<R, 1, VC, true>(p, hval, x, rows, lane, yr, yi, hpos);
+    if (lane == 0 || lane == 3 || lane == 6) {
+      C o;
+      o.x = yr[0];
+      o.y = yi[0];
+      y[3 * (size_t)r0 + lane / 3] = o;
+    }
+  }
+}
+
+// Copy the stored (lower, column <= row) blocks into the half store.
+__global__ void k_gather_half(int64_t nnzb, const int32_t* __restrict__ hpos, const double2* __restrict__ val,
+                              double2* __restrict__ hval) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nnzb * 9) return;
+  const int64_t q = t / 9;
+  const int32_t hp = hpos[q];
+  if (hp < 0) return;
+  hval[(int64_t)hp * 9 + t % 9] = val[t];
+}
 
 template <typename R, typename VC = typename Cx<R>::T>
 __global__ void __launch_bounds__(kBlock) k_spmv(PatternDev p, const VC* __restrict__ val,
@@ -709,6 +754,18 @@ SpmvLaunch spmv_launch_for(int32_t nn, int n_cu) {
   SpmvLaunch L;
   L.blocks = (int)((b + 7) / 8 * 8);
   return L;
+}
+
+hipError_t spmv_half_c128(hipStream_t st, const PatternDev& p, const double2* hval, const int32_t* hpos,
+                          const double2* x, double2* y, SpmvLaunch L) {
+  hipLaunchKernelGGL((k_spmv_half<double>), dim3(L.blocks), dim3(kBlock), 0, st, p, hval, hpos, x, y);
+  return hipGetLastError();
+}
+
+hipError_t gather_half(hipStream_t st, int64_t nnzb, const int32_t* hpos, const double2* val, double2* hval) {
+  const int64_t t = nnzb * 9;
+  hipLaunchKernelGGL(k_gather_half, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, nnzb, hpos, val, hval);
+  return hipGetLastError();
 }
 
 hipError_t spmv_c128(hipStream_t st, const PatternDev& p, const double2* val, const double2* x, double2* y,

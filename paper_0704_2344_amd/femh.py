@@ -140,6 +140,7 @@ SIGNATURES = {
     "femh_spmv_dev": (C.c_int, [P, I32, P, P, I32, PD]),
     "femh_spmm_dev": (C.c_int, [P, I32, I32, P, P, I32, PD]),
     "femh_spmm_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
+    "femh_spmv_half_dev": (C.c_int, [P, P, P, I32, PD]),
     "femh_spmm_set_tile": (C.c_int, [P, I32, I32]),
     "femh_bw_probe": (C.c_int, [P, I64, I32, PD]),
     "femh_profile_enable": (C.c_int, [P, I32]),
@@ -450,6 +451,11 @@ class Problem:
     def spmv_dev(self, x, y, precision=FEMH_FP64, reps=1):
         t = C.c_double()
         check(self.lib.femh_spmv_dev(self.handle, precision, x.data_ptr(), y.data_ptr(), reps, C.byref(t)))
+        return t.value
+
+    def spmv_half_dev(self, x, y, reps=1):
+        t = C.c_double()
+        check(self.lib.femh_spmv_half_dev(self.handle, x.data_ptr(), y.data_ptr(), reps, C.byref(t)))
         return t.value
 
     def spmm_tile(self):
