@@ -25,7 +25,8 @@ Also printed on the same JSON line:
                 to 1e-8): solves/s of each and the quarter's deviation
   serving       a Poisson stream of scattering requests (meshes n^3 with n in
                 [10, serve_n_hi], 1-4 waves each) through the continuous-
-                batching server in matrix-mixed and FP64 precision, and the
+                batching server in matrix-mixed and FP64 precision (each
+                wave its own solve, and a request's waves batched), and the
                 plain FP64 solver one request at a time, all to 1e-6:
                 requests/s, RHS/s, p50/p99 latency from arrival
   roofline      the dominant kernel of the timed steps (the FP64 block SpMV
@@ -91,7 +92,8 @@ def spmm_bytes(nn, nnzb, ncols, s_val=16):
 
 def serving_leg(ctx, F, W, n_requests, rate, n_hi):
     """Replay a Poisson request stream in real time through the server (two
-    precisions) and through the plain FP64 solver one request at a time."""
+    precisions, each wave its own solve, and with a request's waves batched)
+    and through the plain FP64 solver one request at a time."""
     reqs = W.serving_stream(n_requests=n_requests, rate_per_s=rate, seed=46, n_lo=10, n_hi=n_hi, nrhs_hi=4)
     n_rhs = sum(len(r.waves) for r in reqs)
     out = {"workload": (f"{n_requests} requests of the seeded serving stream (Poisson, {rate:g}/s), meshes n^3 "
@@ -103,8 +105,11 @@ def serving_leg(ctx, F, W, n_requests, rate, n_hi):
     t = srv.submit(p0, w0, precision=F.FEMH_FP64, rtol=1e-6)
     srv.poll(t, len(w0), None, want_field=False)
     srv.close()
-    for name, prec in (("server_mixed_matrix", F.FEMH_MIXED_MATRIX), ("server_fp64", F.FEMH_FP64)):
-        srv = F.Server(ctx)
+    for name, prec, batch in (("server_mixed_matrix", F.FEMH_MIXED_MATRIX, False),
+                              ("server_fp64", F.FEMH_FP64, False),
+                              ("server_mixed_matrix_batched", F.FEMH_MIXED_MATRIX, True),
+                              ("server_fp64_batched", F.FEMH_FP64, True)):
+        srv = F.Server(ctx, batch_rhs=batch)
         t0 = time.perf_counter()
         tickets = []
         for r in reqs:
@@ -145,7 +150,9 @@ def serving_leg(ctx, F, W, n_requests, rate, n_hi):
     out["plain_fp64_sequential"] = {"requests_per_s": n_requests / span, "rhs_per_s": n_rhs / span,
                                     "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                                     "failed": bad}
-    out["server_mixed_vs_plain_fp64"] = out["server_mixed_matrix"]["rhs_per_s"] / out["plain_fp64_sequential"]["rhs_per_s"]
+    plain = out["plain_fp64_sequential"]["rhs_per_s"]
+    out["server_mixed_vs_plain_fp64"] = out["server_mixed_matrix"]["rhs_per_s"] / plain
+    out["server_mixed_batched_vs_plain_fp64"] = out["server_mixed_matrix_batched"]["rhs_per_s"] / plain
     return out
 
 

@@ -302,6 +302,11 @@ typedef struct {
   int64_t hbm_budget_bytes;   /* admission limit on resident problem bytes; 0 = 80 % of free */
   int32_t max_slots;          /* resident requests at once; 0 = 32 */
   int32_t chunk_iters;        /* iterations per slot per scheduling round; 0 = 32 */
+  int32_t batch_rhs;          /* 1: a request's waves are solved in groups of up to four, one
+                                 batched solve each (as femh_solve_batched_dev: FP64 directions,
+                                 the complex128 matrix for FEMH_FP64, else the complex64 one);
+                                 0: one single-RHS solve per wave (as femh_solve) */
+  int32_t reserved;           /* 0 */
 } femh_server_opts;
 
 typedef struct {

@@ -28,20 +28,6 @@ namespace {
 
 constexpr size_t kPartialBytes = 2048 * 64 * 4 * sizeof(double);  // [blocks][ld][4] doubles, ld <= 64
 
-struct Scratch {
-  Ctx* ctx;
-  std::vector<void*> ptrs;
-  explicit Scratch(Ctx* c) : ctx(c) {}
-  void* get(size_t bytes) {
-    void* p = ctx->dmalloc(bytes);
-    if (p) ptrs.push_back(p);
-    return p;
-  }
-  ~Scratch() {
-    (void)hipStreamSynchronize(ctx->stream);
-    for (void* p : ptrs) ctx->dfree(p);
-  }
-};
 
 // Process-wide tuning cache: (CU count, log2 of block rows, complex128
 // matrix) -> tile.
@@ -195,103 +181,123 @@ int autotune_spmm(Problem* P, const double2* val64, const double2* Pv, double2* 
   return FEMH_OK;
 }
 
-int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh_solve_opts& o,
-                  femh_solve_stats* st) {
-  Ctx* c = P->ctx;
-  hipStream_t s = c->stream;
-  const int64_t n = 3 * (int64_t)P->pat.nn;
-  // narrow layout for up to four right-hand sides, wide otherwise
-  const int ld = nrhs <= 4 ? 4 : 64;
-  // FEMH_FP64: the complex128 matrix in the product; otherwise the
-  // complex64 matrix promoted
-  const double2* val64 = o.precision == FEMH_FP64 ? P->val64 : nullptr;
-  const size_t v64 = 16 * (size_t)n * ld;
-  Scratch W(c);
-  double2* B64 = (double2*)W.get(v64);
-  double2* X64 = (double2*)W.get(v64);
-  double2* R64 = (double2*)W.get(v64);
-  double2* P64 = (double2*)W.get(v64);
-  double2* Q64 = (double2*)W.get(v64);
-  double* partials = (double*)W.get(kPartialBytes);
-  BatchScalars* sc = (BatchScalars*)W.get(sizeof(BatchScalars));
-  BatchPlan* plan = (BatchPlan*)W.get(sizeof(BatchPlan));
-  BatchPlan* plan_mr = (BatchPlan*)W.get(sizeof(BatchPlan));
-  BatchScalars* run_all = (BatchScalars*)W.get(sizeof(BatchScalars));
-  double* rr64 = (double*)W.get(64 * sizeof(double));
-  if (!B64 || !X64 || !R64 || !P64 || !Q64 || !partials || !sc || !plan || !plan_mr || !run_all || !rr64) {
-    set_error("device allocation failed (batched workspace)");
-    return FEMH_E_OOM;
+// Non-blocking state machine of one batched solve (the serving loop drives
+// several of them together; solve_batched drives one to the end).
+struct BatchStepper {
+  enum Phase { START, WAIT_INIT, ITER, DONE };
+  Problem* P = nullptr;
+  Ctx* c = nullptr;
+  hipStream_t s = nullptr;
+  int nrhs = 0;
+  const double2* b = nullptr;
+  double2* x = nullptr;
+  femh_solve_opts o{};
+  int64_t n = 0;
+  int ld = 4;
+  size_t v64 = 0;
+  const double2* val64 = nullptr;  // complex128 matrix in the product, or null (complex64 promoted)
+  std::vector<void*> owned;
+  double2 *B64 = nullptr, *X64 = nullptr, *R64 = nullptr, *P64 = nullptr, *Q64 = nullptr;
+  double* partials = nullptr;
+  BatchScalars *sc = nullptr, *run_all = nullptr;
+  BatchPlan *plan = nullptr, *plan_mr = nullptr;
+  double* rr64 = nullptr;
+  const double2* dinv = nullptr;
+  int vblocks = 0, rblocks = 0;
+  BatchTile tile{2, 0};
+  // pinned host mirrors: scalar block, the always-active block, residual norms
+  void* pinned = nullptr;
+  BatchScalars* hs = nullptr;
+  BatchScalars* ra = nullptr;
+  double* hrr = nullptr;
+  BatchPlan hp{};
+  std::vector<int> updates, final_status;
+  std::vector<double> rel, bb;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = false;
+  hipEvent_t ready = nullptr, ev_init = nullptr;
+  bool queued = false;  // a scalar readback (and the chunk behind it) is in flight
+  int guard = 0;
+  int status = FEMH_OK;
+  Phase phase = START;
+
+  void* dev(size_t bytes) {
+    void* p = c->dmalloc(bytes);
+    if (p) owned.push_back(p);
+    return p;
   }
-  const double2* dinv = P->dinv64;
-  if (o.precond == FEMH_PRECOND_NONE) {
-    double2* ones = (double2*)W.get(16 * n);
-    if (!ones) {
-      set_error("device allocation failed (identity preconditioner)");
+
+  ~BatchStepper() {
+    if (!c) return;
+    (void)hipStreamSynchronize(s);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ready) (void)hipEventDestroy(ready);
+    if (ev_init) (void)hipEventDestroy(ev_init);
+    if (pinned) (void)hipHostFree(pinned);
+    for (void* p : owned) c->dfree(p);
+  }
+
+  int init(Problem* prob, int nrhs_, const double2* b_, double2* x_, const femh_solve_opts& opts) {
+    P = prob;
+    c = prob->ctx;
+    s = c->stream;
+    nrhs = nrhs_;
+    b = b_;
+    x = x_;
+    o = opts;
+    n = 3 * (int64_t)P->pat.nn;
+    // narrow layout for up to four right-hand sides, wide otherwise
+    ld = nrhs <= 4 ? 4 : 64;
+    // FEMH_FP64: the complex128 matrix in the product; otherwise the
+    // complex64 matrix promoted
+    val64 = o.precision == FEMH_FP64 ? P->val64 : nullptr;
+    v64 = 16 * (size_t)n * ld;
+    B64 = (double2*)dev(v64);
+    X64 = (double2*)dev(v64);
+    R64 = (double2*)dev(v64);
+    P64 = (double2*)dev(v64);
+    Q64 = (double2*)dev(v64);
+    partials = (double*)dev(kPartialBytes);
+    sc = (BatchScalars*)dev(sizeof(BatchScalars));
+    plan = (BatchPlan*)dev(sizeof(BatchPlan));
+    plan_mr = (BatchPlan*)dev(sizeof(BatchPlan));
+    run_all = (BatchScalars*)dev(sizeof(BatchScalars));
+    rr64 = (double*)dev(64 * sizeof(double));
+    if (!B64 || !X64 || !R64 || !P64 || !Q64 || !partials || !sc || !plan || !plan_mr || !run_all || !rr64) {
+      set_error("device allocation failed (batched workspace)");
       return FEMH_E_OOM;
     }
-    std::vector<double2> h((size_t)n, make_double2(1.0, 0.0));
-    FEMH_TRY_HIP(hipMemcpyAsync(ones, h.data(), 16 * n, hipMemcpyHostToDevice, s));
-    FEMH_TRY_HIP(hipStreamSynchronize(s));
-    dinv = ones;
-  }
-  const int vblocks = k::batched_vec_blocks(n, ld);
-  const int rblocks = k::batched_blocks_for(P->pat.nn, c->n_cu, 4);
-
-  hipEvent_t t0, t1;
-  FEMH_TRY_HIP(hipEventCreate(&t0));
-  FEMH_TRY_HIP(hipEventCreate(&t1));
-  FEMH_TRY_HIP(hipEventRecord(t0, s));
-
-  FEMH_TRY_HIP(k::to_block(s, n, ld, nrhs, b, B64));
-  FEMH_TRY_HIP(hipMemsetAsync(X64, 0, v64, s));
-  FEMH_TRY_HIP(hipMemsetAsync(P64, 0, v64, s));
-  FEMH_TRY_HIP(k::bresidual64(s, P->pat, ld, P->val64, X64, B64, R64, partials, rblocks, rr64, nullptr));
-  std::vector<double> hrr(64), bb(64);
-  FEMH_TRY_HIP(hipMemcpyAsync(hrr.data(), rr64, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
-  FEMH_TRY_HIP(hipStreamSynchronize(s));
-
-  // host mirrors (pinned scalar block for the per-chunk reads)
-  BatchScalars* hs = reinterpret_cast<BatchScalars*>(c->pinned);
-  static_assert(sizeof(BatchScalars) <= 16384, "pinned scratch too small");
-  BatchPlan hp;
-  std::memset(hs, 0, sizeof(*hs));
-  std::memset(&hp, 0, sizeof(hp));
-  hs->max_iters = o.max_iter;
-  hs->delta2 = o.inner_rtol * o.inner_rtol;
-  hs->bd_tol = 1e-13;  // FP64 residual recurrence: only genuine breakdowns
-  std::vector<int> updates(64, 0), final_status(64, FEMH_OK);
-  std::vector<double> rel(64, 0.0);
-  for (int col = 0; col < 64; ++col) {
-    bb[col] = col < nrhs ? hrr[col] : 0.0;
-    if (bb[col] > 0.0) {
-      hs->done[col] = 0;
-      hp.action[col] = 2;
-      hp.tol2[col] = o.rtol * o.rtol * bb[col];
-      rel[col] = 1.0;
-    } else {
-      hs->done[col] = 5;
-      hp.action[col] = 0;
+    dinv = P->dinv64;
+    if (o.precond == FEMH_PRECOND_NONE) {
+      double2* ones = (double2*)dev(16 * n);
+      if (!ones) {
+        set_error("device allocation failed (identity preconditioner)");
+        return FEMH_E_OOM;
+      }
+      std::vector<double2> h((size_t)n, make_double2(1.0, 0.0));
+      FEMH_TRY_HIP(hipMemcpyAsync(ones, h.data(), 16 * n, hipMemcpyHostToDevice, s));
+      FEMH_TRY_HIP(hipStreamSynchronize(s));
+      dinv = ones;
     }
-  }
-  FEMH_TRY_HIP(hipMemcpyAsync(sc, hs, sizeof(*hs), hipMemcpyHostToDevice, s));
-  FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
-  FEMH_TRY_HIP(k::brescale(s, n, ld, R64, dinv, P64, partials, vblocks, sc, plan));
-  {
-    BatchScalars* ra = reinterpret_cast<BatchScalars*>(static_cast<char*>(c->pinned) + 8192);
-    static_assert(2 * sizeof(BatchScalars) <= 16384, "pinned scratch too small");
-    std::memset(ra, 0, sizeof(*ra));
-    ra->active = 1;
-    FEMH_TRY_HIP(hipMemcpyAsync(run_all, ra, sizeof(*ra), hipMemcpyHostToDevice, s));
-  }
-  FEMH_TRY_HIP(hipStreamSynchronize(s));
-  BatchTile tile{2, P->spmv.blocks};  // narrow product: the single-RHS SpMV's grid
-  if (ld == 64) {
-    FEMH_TRY(autotune_spmm(P, val64, P64, Q64, partials, sc));
-    tile = P->tile;
+    static_assert(2 * sizeof(BatchScalars) + 64 * sizeof(double) <= 32768, "pinned block too small");
+    FEMH_TRY_HIP(hipHostMalloc(&pinned, 32768, hipHostMallocDefault));
+    hs = reinterpret_cast<BatchScalars*>(pinned);
+    ra = reinterpret_cast<BatchScalars*>(static_cast<char*>(pinned) + 12288);
+    hrr = reinterpret_cast<double*>(static_cast<char*>(pinned) + 24576);
+    FEMH_TRY_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    FEMH_TRY_HIP(hipEventCreateWithFlags(&ev_init, hipEventDisableTiming));
+    vblocks = k::batched_vec_blocks(n, ld);
+    rblocks = k::batched_blocks_for(P->pat.nn, c->n_cu, 4);
+    updates.assign(64, 0);
+    final_status.assign(64, FEMH_OK);
+    rel.assign(64, 0.0);
+    bb.assign(64, 0.0);
+    return FEMH_OK;
   }
 
-  // one chunk of iterations, captured once
-  auto launch_chunk = [&]() -> hipError_t {
+  hipError_t launch_chunk() {
     for (int i = 0; i < o.check_every; ++i) {
       hipError_t e;
       if ((e = k::bspmm(s, P->pat, P->val32, val64, P64, Q64, partials, sc, tile)) != hipSuccess) return e;
@@ -301,45 +307,69 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
       if ((e = k::bpupdate(s, n, ld, dinv, R64, P64, vblocks, sc, nullptr)) != hipSuccess) return e;
     }
     return hipSuccess;
-  };
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  bool use_graph = true;
-  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-    hipError_t e = launch_chunk();
-    hipError_t e2 = hipStreamEndCapture(s, &graph);
-    if (e != hipSuccess || e2 != hipSuccess || !graph ||
-        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
-      use_graph = false;
-  } else {
-    use_graph = false;
   }
-  (void)hipGetLastError();
-  auto run_chunk = [&]() -> hipError_t { return use_graph ? hipGraphLaunch(exec, s) : launch_chunk(); };
 
-  hipEvent_t ready;
-  FEMH_TRY_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-  int status = FEMH_OK;
-  int guard = 0;
-  FEMH_TRY_HIP(run_chunk());
-  while (true) {
-    FEMH_TRY_HIP(hipMemcpyAsync(hs, sc, sizeof(*hs), hipMemcpyDeviceToHost, s));
-    FEMH_TRY_HIP(hipEventRecord(ready, s));
-    FEMH_TRY_HIP(run_chunk());
-    FEMH_TRY_HIP(hipEventSynchronize(ready));
-    bool pending = false, running = false;
+  hipError_t run_chunk() { return use_graph ? hipGraphLaunch(exec, s) : launch_chunk(); }
+
+  // x = 0, r = b and the columns' ||b||^2
+  int start() {
+    FEMH_TRY_HIP(k::to_block(s, n, ld, nrhs, b, B64));
+    FEMH_TRY_HIP(hipMemsetAsync(X64, 0, v64, s));
+    FEMH_TRY_HIP(hipMemsetAsync(P64, 0, v64, s));
+    FEMH_TRY_HIP(k::bresidual64(s, P->pat, ld, P->val64, X64, B64, R64, partials, rblocks, rr64, nullptr));
+    FEMH_TRY_HIP(hipMemcpyAsync(hrr, rr64, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
+    FEMH_TRY_HIP(hipEventRecord(ev_init, s));
+    phase = WAIT_INIT;
+    return FEMH_OK;
+  }
+
+  int begin_iterating() {
+    std::memset(hs, 0, sizeof(*hs));
+    std::memset(&hp, 0, sizeof(hp));
+    hs->max_iters = o.max_iter;
+    hs->delta2 = o.inner_rtol * o.inner_rtol;
+    hs->bd_tol = 1e-13;  // FP64 residual recurrence: only genuine breakdowns
     for (int col = 0; col < 64; ++col) {
-      const int d = hs->done[col];
-      if (d >= 1 && d <= 4) pending = true;
-      if (d == 0) running = true;
+      bb[col] = col < nrhs ? hrr[col] : 0.0;
+      if (bb[col] > 0.0) {
+        hs->done[col] = 0;
+        hp.action[col] = 2;
+        hp.tol2[col] = o.rtol * o.rtol * bb[col];
+        rel[col] = 1.0;
+      } else {
+        hs->done[col] = 5;
+        hp.action[col] = 0;
+      }
     }
-    if (!pending && !running) break;
-    if (++guard > 2 * (o.max_iter / std::max(o.check_every, 1) + 2) + 4096) {
-      status = FEMH_E_NOT_CONVERGED;
-      break;
+    FEMH_TRY_HIP(hipMemcpyAsync(sc, hs, sizeof(*hs), hipMemcpyHostToDevice, s));
+    FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
+    FEMH_TRY_HIP(k::brescale(s, n, ld, R64, dinv, P64, partials, vblocks, sc, plan));
+    std::memset(ra, 0, sizeof(*ra));
+    ra->active = 1;
+    FEMH_TRY_HIP(hipMemcpyAsync(run_all, ra, sizeof(*ra), hipMemcpyHostToDevice, s));
+    FEMH_TRY_HIP(hipStreamSynchronize(s));
+    tile = BatchTile{2, P->spmv.blocks};  // narrow product: the single-RHS SpMV's grid
+    if (ld == 64) {
+      FEMH_TRY(autotune_spmm(P, val64, P64, Q64, partials, sc));
+      tile = P->tile;
     }
-    if (!pending) continue;
-    // ---- reliable update of the flagged columns
+    // one chunk of iterations, captured once
+    use_graph = false;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      hipError_t e = launch_chunk();
+      hipError_t e2 = hipStreamEndCapture(s, &graph);
+      use_graph = e == hipSuccess && e2 == hipSuccess && graph &&
+                  hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    }
+    (void)hipGetLastError();
+    FEMH_TRY_HIP(run_chunk());
+    phase = ITER;
+    return FEMH_OK;
+  }
+
+  // Reliable update of the columns that asked for one (reads back the FP64
+  // true residual norms, so it waits on the stream).
+  int reliable_update() {
     std::memset(&hp, 0, sizeof(hp));
     int flagged[64];
     for (int col = 0; col < 64; ++col) {
@@ -350,7 +380,7 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
     FEMH_TRY_HIP(hipMemcpyAsync(plan, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
     // true residual into the flagged columns only
     FEMH_TRY_HIP(k::bresidual64(s, P->pat, ld, P->val64, X64, B64, R64, partials, rblocks, rr64, plan->action));
-    FEMH_TRY_HIP(hipMemcpyAsync(hrr.data(), rr64, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
+    FEMH_TRY_HIP(hipMemcpyAsync(hrr, rr64, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
     FEMH_TRY_HIP(hipStreamSynchronize(s));
     std::memset(&hp, 0, sizeof(hp));
     for (int col = 0; col < 64; ++col) {
@@ -393,28 +423,128 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
     FEMH_TRY_HIP(k::brescale(s, n, ld, R64, dinv, P64, partials, vblocks, sc, plan));
     FEMH_TRY_HIP(k::bpupdate(s, n, ld, dinv, R64, P64, vblocks, sc, plan->action));
     FEMH_TRY_HIP(run_chunk());
+    return FEMH_OK;
   }
-  FEMH_TRY_HIP(hipStreamSynchronize(s));
-  (void)hipEventDestroy(ready);
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
-  FEMH_TRY_HIP(k::from_block(s, n, ld, nrhs, X64, x));
-  FEMH_TRY_HIP(hipEventRecord(t1, s));
-  FEMH_TRY_HIP(hipEventSynchronize(t1));
+
+  int finish() {
+    FEMH_TRY_HIP(hipStreamSynchronize(s));
+    FEMH_TRY_HIP(k::from_block(s, n, ld, nrhs, X64, x));
+    phase = DONE;
+    return FEMH_OK;
+  }
+
+  // Advance without blocking except inside a reliable update; *progress is
+  // set when something moved.
+  int step(bool* progress) {
+    *progress = false;
+    switch (phase) {
+      case START:
+        *progress = true;
+        return start();
+      case WAIT_INIT:
+        if (hipEventQuery(ev_init) != hipSuccess) return FEMH_OK;
+        *progress = true;
+        return begin_iterating();
+      case ITER: {
+        if (!queued) {
+          // read the scalars behind the chunk in flight, one more chunk queued ahead
+          FEMH_TRY_HIP(hipMemcpyAsync(hs, sc, sizeof(*hs), hipMemcpyDeviceToHost, s));
+          FEMH_TRY_HIP(hipEventRecord(ready, s));
+          FEMH_TRY_HIP(run_chunk());
+          queued = true;
+          *progress = true;
+        }
+        if (hipEventQuery(ready) != hipSuccess) return FEMH_OK;
+        queued = false;
+        *progress = true;
+        bool pending = false, running = false;
+        for (int col = 0; col < 64; ++col) {
+          const int d = hs->done[col];
+          if (d >= 1 && d <= 4) pending = true;
+          if (d == 0) running = true;
+        }
+        if (!pending && !running) return finish();
+        if (++guard > 2 * (o.max_iter / std::max(o.check_every, 1) + 2) + 4096) {
+          status = FEMH_E_NOT_CONVERGED;
+          return finish();
+        }
+        if (pending) return reliable_update();
+        return FEMH_OK;
+      }
+      case DONE:
+        return FEMH_OK;
+    }
+    return FEMH_OK;
+  }
+
+  void wait() {
+    if (phase == WAIT_INIT) (void)hipEventSynchronize(ev_init);
+    else if (phase == ITER && queued) (void)hipEventSynchronize(ready);
+  }
+
+  // per-column stats; returns the first failing status (FEMH_OK if none)
+  int fill_stats(femh_solve_stats* st) const {
+    int first = status;
+    for (int col = 0; col < nrhs; ++col) {
+      std::memset(&st[col], 0, sizeof(st[col]));
+      st[col].status = bb[col] > 0.0 ? final_status[col] : FEMH_OK;
+      st[col].iters = hs->iters[col];
+      st[col].outer_iters = updates[col];
+      st[col].rel_residual = bb[col] > 0.0 ? rel[col] : 0.0;
+      if (hs->done[col] < 5 && bb[col] > 0.0) st[col].status = FEMH_E_NOT_CONVERGED;
+      if (st[col].status != FEMH_OK && first == FEMH_OK) first = st[col].status;
+    }
+    return first;
+  }
+};
+
+BatchStepper* batch_stepper_create(Problem* P, int nrhs, const double2* b, double2* x, const femh_solve_opts& o) {
+  BatchStepper* s = new BatchStepper();
+  if (s->init(P, nrhs, b, x, o) != FEMH_OK) {
+    delete s;
+    return nullptr;
+  }
+  return s;
+}
+int batch_stepper_step(BatchStepper* s, bool* progress) { return s->step(progress); }
+bool batch_stepper_done(const BatchStepper* s) { return s->phase == BatchStepper::DONE; }
+void batch_stepper_wait(BatchStepper* s) { s->wait(); }
+int batch_stepper_stats(const BatchStepper* s, femh_solve_stats* st) { return s->fill_stats(st); }
+void batch_stepper_destroy(BatchStepper* s) { delete s; }
+
+int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh_solve_opts& o,
+                  femh_solve_stats* st) {
+  Ctx* c = P->ctx;
+  hipEvent_t t0, t1;
+  FEMH_TRY_HIP(hipEventCreate(&t0));
+  FEMH_TRY_HIP(hipEventCreate(&t1));
+  FEMH_TRY_HIP(hipEventRecord(t0, c->stream));
+  BatchStepper* S = batch_stepper_create(P, nrhs, b, x, o);
+  if (!S) {
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return FEMH_E_OOM;
+  }
+  int rc = FEMH_OK;
+  while (!batch_stepper_done(S)) {
+    bool progress = false;
+    rc = S->step(&progress);
+    if (rc != FEMH_OK) break;
+    if (!progress) S->wait();
+  }
+  (void)hipEventRecord(t1, c->stream);
+  (void)hipEventSynchronize(t1);
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, t0, t1);
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  for (int col = 0; col < nrhs; ++col) {
-    std::memset(&st[col], 0, sizeof(st[col]));
-    st[col].status = bb[col] > 0.0 ? final_status[col] : FEMH_OK;
-    st[col].iters = hs->iters[col];
-    st[col].outer_iters = updates[col];
-    st[col].rel_residual = bb[col] > 0.0 ? rel[col] : 0.0;
-    st[col].seconds = ms * 1e-3;
-    if (hs->done[col] < 5 && bb[col] > 0.0) st[col].status = FEMH_E_NOT_CONVERGED;
-    if (st[col].status != FEMH_OK && status == FEMH_OK) status = st[col].status;
+  if (rc != FEMH_OK) {
+    delete S;
+    return rc;
   }
+  const int status = S->fill_stats(st);
+  for (int col = 0; col < nrhs; ++col) st[col].seconds = ms * 1e-3;
+  delete S;
   if (status != FEMH_OK) set_error("batched solve: at least one column did not converge");
   return status;
 }

@@ -316,6 +316,8 @@ struct Problem {
 int validate_desc(const femh_problem_desc* d, std::string& msg);
 int validate_waves(int32_t nrhs, const femh_plane_wave* w, std::string& msg);
 int64_t estimate_bytes(const femh_problem_desc* d, int32_t nrhs, int32_t precision);
+// Extra device bytes of solving nrhs waves as batched groups of up to four.
+int64_t estimate_batch_workspace(const femh_problem_desc* d, int32_t nrhs);
 int problem_create(Ctx* ctx, const femh_problem_desc* d, Problem** out);
 femh_solve_opts opts_with_defaults(const femh_solve_opts* o);
 
@@ -343,6 +345,17 @@ int ensure_half_store(Problem* P);
 // Single-RHS solve as a non-blocking state machine (one code path for
 // femh_solve and the server).  step() queues the work its phase allows and
 // acts on readbacks that have landed; wait() blocks on the oldest one.
+// Non-blocking batched solve of nrhs (<= 64) right-hand sides b (device,
+// [nrhs][n]) into x: the state machine solve_batched drives to the end,
+// and the serving loop interleaves with other requests.
+struct BatchStepper;
+BatchStepper* batch_stepper_create(Problem* P, int nrhs, const double2* b, double2* x, const femh_solve_opts& o);
+int batch_stepper_step(BatchStepper* s, bool* progress);
+bool batch_stepper_done(const BatchStepper* s);
+void batch_stepper_wait(BatchStepper* s);
+int batch_stepper_stats(const BatchStepper* s, femh_solve_stats* st);  // first failing status
+void batch_stepper_destroy(BatchStepper* s);
+
 struct Stepper;
 Stepper* stepper_create(Problem* P, const double2* b, double2* x, const femh_solve_opts& o);
 int stepper_step(Stepper* s, bool* progress);

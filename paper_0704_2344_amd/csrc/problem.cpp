@@ -237,6 +237,15 @@ int64_t estimate_bytes(const femh_problem_desc* d, int32_t nrhs, int32_t precisi
   return b;
 }
 
+int64_t estimate_batch_workspace(const femh_problem_desc* d, int32_t nrhs) {
+  int64_t nn, nnzb;
+  count_pattern(d, nn, nnzb);
+  // per group of up to four waves: five [unknowns][4] complex128 blocks,
+  // the per-workgroup partial sums (2048 x 64 x 4 doubles) and small blocks
+  const int64_t groups = (nrhs + 3) / 4;
+  return groups * (5 * al(4 * 48 * nn) + (4 << 20) + (1 << 16));
+}
+
 // --------------------------------------------------------- problem create
 static void fill_mesh(MeshDev& m, const femh_problem_desc* d) {
   m.nx = d->nx;

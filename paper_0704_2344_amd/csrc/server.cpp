@@ -53,6 +53,9 @@ struct Request {
   double2* b = nullptr;
   double2* x = nullptr;
   std::vector<femh::Stepper*> steps;
+  // batch_rhs: the waves in groups of up to four, one batched solve each
+  std::vector<femh::BatchStepper*> bsteps;
+  std::vector<int> bfirst;  // first wave of each group
 };
 
 }  // namespace
@@ -63,6 +66,7 @@ struct femh_server {
   int64_t budget = 0;
   int max_slots = 32;
   int chunk = 32;
+  bool batch_rhs = false;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> queue;
@@ -89,6 +93,9 @@ namespace {
 void release(Request* r) {
   for (femh::Stepper* s : r->steps) femh::stepper_destroy(s);
   r->steps.clear();
+  for (femh::BatchStepper* s : r->bsteps) femh::batch_stepper_destroy(s);
+  r->bsteps.clear();
+  r->bfirst.clear();
   if (r->lane) {
     if (r->b) r->lane->dfree(r->b);
     if (r->x) r->lane->dfree(r->x);
@@ -163,6 +170,23 @@ int femh_server::setup(Request* r) {
     femh::set_error("request set-up failed: %s", hipGetErrorString(e));
     return FEMH_E_DEVICE;
   }
+  r->stats.assign(nrhs, femh_solve_stats{});
+  if (batch_rhs && nrhs >= 2) {
+    // the batched solver's options, as femh_solve_batched_dev sets them
+    femh_solve_opts ob = r->opts;
+    if (ob.precision != FEMH_FP64) ob.precision = FEMH_MIXED_MATRIX;
+    if (ob.inner_rtol <= 0.0) ob.inner_rtol = 1e-3;
+    femh_solve_opts o = femh::opts_with_defaults(&ob);
+    if (r->opts.check_every <= 0) o.check_every = chunk;
+    for (int g = 0; g < nrhs; g += 4) {
+      const int k = std::min(4, nrhs - g);
+      femh::BatchStepper* s = femh::batch_stepper_create(r->P, k, r->b + g * n, r->x + g * n, o);
+      if (!s) return FEMH_E_OOM;
+      r->bsteps.push_back(s);
+      r->bfirst.push_back(g);
+    }
+    return FEMH_OK;
+  }
   femh_solve_opts o = femh::opts_with_defaults(&r->opts);
   if (r->opts.check_every <= 0) o.check_every = chunk;
   for (int k = 0; k < nrhs; ++k) {
@@ -170,7 +194,6 @@ int femh_server::setup(Request* r) {
     if (!s) return FEMH_E_OOM;
     r->steps.push_back(s);
   }
-  r->stats.assign(nrhs, femh_solve_stats{});
   return FEMH_OK;
 }
 
@@ -181,6 +204,12 @@ void femh_server::retire(Request* r, int status) {
       femh::stepper_stats(r->steps[k], &r->stats[k]);
       r->stats[k].seconds = now_s() - r->t_start;
       if (r->stats[k].status != FEMH_OK && status == FEMH_OK) status = r->stats[k].status;
+    }
+    for (size_t g = 0; g < r->bsteps.size(); ++g) {
+      const int first = r->bfirst[g];
+      const int st = femh::batch_stepper_stats(r->bsteps[g], &r->stats[first]);
+      for (int k = first; k < std::min(nrhs, first + 4); ++k) r->stats[k].seconds = now_s() - r->t_start;
+      if (st != FEMH_OK && status == FEMH_OK) status = st;
     }
     // field to the grid, then to host memory
     femh::Ctx* c = r->lane;
@@ -246,8 +275,9 @@ void femh_server::loop() {
     }
     bool any_progress = false;
     femh::Stepper* waiter = nullptr;
+    femh::BatchStepper* bwaiter = nullptr;
     for (Request* r : active) {
-      if (r->state != Request::RUNNING || r->steps.empty()) continue;
+      if (r->state != Request::RUNNING || (r->steps.empty() && r->bsteps.empty())) continue;
       bool cancel;
       {
         std::lock_guard<std::mutex> g(mu);
@@ -271,7 +301,22 @@ void femh_server::loop() {
         any_progress |= prog;
         if (!femh::stepper_done(s)) {
           all_done = false;
-          if (!waiter) waiter = s;
+          if (!waiter && !bwaiter) waiter = s;
+        }
+      }
+      for (femh::BatchStepper* s : r->bsteps) {
+        if (err != FEMH_OK) break;
+        if (femh::batch_stepper_done(s)) continue;
+        bool prog = false;
+        const int rc = femh::batch_stepper_step(s, &prog);
+        if (rc != FEMH_OK) {
+          err = rc;
+          break;
+        }
+        any_progress |= prog;
+        if (!femh::batch_stepper_done(s)) {
+          all_done = false;
+          if (!waiter && !bwaiter) bwaiter = s;
         }
       }
       if (err != FEMH_OK) {
@@ -282,6 +327,7 @@ void femh_server::loop() {
       }
     }
     if (!any_progress && waiter) femh::stepper_wait(waiter);
+    if (!any_progress && bwaiter) femh::batch_stepper_wait(bwaiter);
   }
   // shut down: cancel whatever is left
   std::vector<Request*> left;
@@ -304,8 +350,8 @@ int femh_server_create(femh_ctx* ctx_, const femh_server_opts* opts, femh_server
   *out = nullptr;
   femh_server_opts o{};
   if (opts) o = *opts;
-  if (o.hbm_budget_bytes < 0 || o.max_slots < 0 || o.chunk_iters < 0) {
-    femh::set_error("server options must be >= 0");
+  if (o.hbm_budget_bytes < 0 || o.max_slots < 0 || o.chunk_iters < 0 || o.batch_rhs < 0 || o.batch_rhs > 1) {
+    femh::set_error("server options must be >= 0 (batch_rhs 0 or 1)");
     return FEMH_E_INVALID;
   }
   FEMH_TRY_HIP(hipSetDevice(ctx->device));
@@ -324,6 +370,7 @@ int femh_server_create(femh_ctx* ctx_, const femh_server_opts* opts, femh_server
   }
   s->max_slots = o.max_slots > 0 ? o.max_slots : 32;
   s->chunk = o.chunk_iters > 0 ? o.chunk_iters : 32;
+  s->batch_rhs = o.batch_rhs != 0;
   const int nlanes = 4;
   for (int i = 0; i < nlanes; ++i) {
     femh::Ctx* c = new femh::Ctx();
@@ -376,8 +423,10 @@ int femh_server_submit(femh_server* s, const femh_problem_desc* desc, int32_t nr
   r->waves.assign(waves, waves + nrhs);
   if (opts) r->opts = *opts;
   const femh_solve_opts o = femh::opts_with_defaults(opts);
-  // problem + per-column solver workspace
-  const int64_t base = femh::estimate_bytes(desc, nrhs, o.precision);
+  // problem + per-column solver workspace (+ the batched groups' blocks;
+  // batch_rhs is fixed when the server is created)
+  int64_t base = femh::estimate_bytes(desc, nrhs, o.precision);
+  if (s->batch_rhs && nrhs >= 2) base += femh::estimate_batch_workspace(desc, nrhs);
   r->est_bytes = base;
   std::lock_guard<std::mutex> g(s->mu);
   ++s->submitted;

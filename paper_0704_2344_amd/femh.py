@@ -95,7 +95,8 @@ class femh_problem_info(C.Structure):
 
 
 class femh_server_opts(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("chunk_iters", C.c_int32)]
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("chunk_iters", C.c_int32),
+                ("batch_rhs", C.c_int32), ("reserved", C.c_int32)]
 
 
 class femh_server_report(C.Structure):
@@ -476,10 +477,10 @@ class Problem:
 class Server:
     """Continuous-batching request loop (femh_server_*)."""
 
-    def __init__(self, ctx: Context, hbm_budget_bytes=0, max_slots=0, chunk_iters=0):
+    def __init__(self, ctx: Context, hbm_budget_bytes=0, max_slots=0, chunk_iters=0, batch_rhs=False):
         self.ctx = ctx
         self.lib = ctx.lib
-        o = femh_server_opts(hbm_budget_bytes, max_slots, chunk_iters)
+        o = femh_server_opts(hbm_budget_bytes, max_slots, chunk_iters, int(bool(batch_rhs)), 0)
         h = C.c_void_p()
         check(self.lib.femh_server_create(ctx.handle, C.byref(o), C.byref(h)))
         self.handle = h

@@ -113,3 +113,48 @@ def test_three_precisions_grouped_match_plain_solves(ctx):
         np.testing.assert_array_equal(H, H1)
         assert [s["iters"] for s in stats] == [s["iters"] for s in s1]
         P.close()
+
+
+@pytest.mark.parametrize("prec", [F.FEMH_MIXED_MATRIX, F.FEMH_FP64])
+def test_batch_rhs_requests_same_alone_in_mix_and_batched(ctx, prec):
+    """With batch_rhs, a request's waves are solved in groups of up to four by
+    the batched solver: each field is bit-identical alone, in a mix of
+    requests that overlap on the device, and to femh_solve_batched_dev on the
+    same group of waves; and within 1e-6 of the plain single-RHS solve."""
+    import torch
+    rng = np.random.default_rng(8)
+    reqs = [W.serving_request(rng, n_lo=8, n_hi=16, nrhs_hi=3) for _ in range(5)]
+    p6, w6 = W.pec_sphere_batched(n=12, radius=0.3, nrhs=6, seed=12)   # groups of 4 + 2
+    reqs.append((p6, w6))
+    opts = dict(precision=prec, rtol=1e-7, check_every=16)
+    srv = F.Server(ctx, max_slots=8, chunk_iters=16, batch_rhs=True)
+    alone = []
+    for p, w in reqs[:2]:
+        t = srv.submit(p, w, **opts)
+        st, H, stats = srv.poll(t, len(w), _shape(p, len(w)))
+        assert st == F.FEMH_OK, stats
+        alone.append(H)
+    tickets = [srv.submit(p, w, **opts) for p, w in reqs]
+    fields = []
+    for (p, w), t in zip(reqs, tickets):
+        st, H, stats = srv.poll(t, len(w), _shape(p, len(w)))
+        assert st == F.FEMH_OK, stats
+        fields.append(H)
+    assert srv.report()["failed"] == 0
+    srv.close()
+    for a, H in zip(alone, fields[:2]):
+        np.testing.assert_array_equal(a, H)
+    for (p, w), H in zip(reqs, fields):
+        P = F.Problem(ctx, p)
+        if len(w) >= 2:
+            for g in range(0, len(w), 4):
+                ww = w[g:g + 4]
+                out = torch.zeros(P.grid_shape(len(ww)), dtype=torch.complex128, device="cuda")
+                s, st = P.solve_dev(ww, out, batched=True, **opts)
+                assert st == F.FEMH_OK, s
+                np.testing.assert_array_equal(out.cpu().numpy(), H[g:g + 4])
+        Hs, s1, st1 = P.solve(w, precision=F.FEMH_FP64, rtol=1e-9)
+        assert st1 == F.FEMH_OK
+        for r in range(len(w)):
+            assert np.linalg.norm(H[r] - Hs[r]) / np.linalg.norm(Hs[r]) <= 1e-6
+        P.close()
