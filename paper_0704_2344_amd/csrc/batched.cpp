@@ -83,54 +83,6 @@ int ensure_row_order(Problem* P) {
   return FEMH_OK;
 }
 
-// Symmetric half store of the complex-symmetric matrix (A_ba = A_ab^T per
-// block): each row keeps its blocks with column <= row, a prefix of the
-// row since columns ascend.  Slot k of row a with column b points at the
-// stored block: row a's own (b <= a), or row b's block for column a read
-// transposed (b > a).  Built on the host from the pattern.
-int ensure_half_store(Problem* P) {
-  if (P->hpos) return FEMH_OK;
-  const int32_t nn = P->pat.nn;
-  const int64_t nnzb = P->pat.nnzb;
-  std::vector<int32_t> rp((size_t)nn + 1), ci((size_t)nnzb), hp((size_t)nnzb);
-  FEMH_TRY_HIP(hipMemcpy(rp.data(), P->row_ptr, sizeof(int32_t) * (nn + 1), hipMemcpyDeviceToHost));
-  FEMH_TRY_HIP(hipMemcpy(ci.data(), P->col_idx, sizeof(int32_t) * nnzb, hipMemcpyDeviceToHost));
-  std::vector<int64_t> hrow((size_t)nn + 1, 0);
-  for (int32_t a = 0; a < nn; ++a) {
-    int32_t lower = 0;
-    for (int32_t k = rp[a]; k < rp[a + 1] && ci[k] <= a; ++k) ++lower;
-    hrow[a + 1] = hrow[a] + lower;
-  }
-  for (int32_t a = 0; a < nn; ++a)
-    for (int32_t k = rp[a]; k < rp[a + 1]; ++k) {
-      const int32_t b = ci[k];
-      if (b <= a) {
-        hp[k] = (int32_t)(hrow[a] + (k - rp[a]));
-      } else {
-        int32_t r = rp[b];
-        while (r < rp[b + 1] && ci[r] != a) ++r;
-        if (r == rp[b + 1]) {
-          set_error("matrix pattern is not symmetric");
-          return FEMH_E_INVALID;
-        }
-        hp[k] = -(int32_t)(hrow[b] + (r - rp[b])) - 1;
-      }
-    }
-  int32_t* dpos = (int32_t*)P->alloc(sizeof(int32_t) * nnzb);
-  double2* dval = (double2*)P->alloc(sizeof(double2) * 9 * (size_t)hrow[nn]);
-  if (!dpos || !dval) {
-    set_error("device allocation failed (half store)");
-    return FEMH_E_OOM;
-  }
-  FEMH_TRY_HIP(hipMemcpy(dpos, hp.data(), sizeof(int32_t) * nnzb, hipMemcpyHostToDevice));
-  FEMH_TRY_HIP(k::gather_half(P->ctx->stream, nnzb, dpos, P->val64, dval));
-  FEMH_TRY_HIP(hipStreamSynchronize(P->ctx->stream));
-  P->hpos = dpos;
-  P->hval64 = dval;
-  P->n_half = hrow[nn];
-  return FEMH_OK;
-}
-
 int autotune_spmm(Problem* P, const double2* val64, const double2* Pv, double2* Qv, double* partials,
                   const BatchScalars* sc) {
   FEMH_TRY(ensure_row_order(P));
