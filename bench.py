@@ -336,8 +336,8 @@ def main():
         p3, w3 = W.pec_sphere_batched(40)
         P3 = F.Problem(ctx, p3)
         o3 = torch.zeros(P3.grid_shape(64), dtype=torch.complex128, device=dev)
-        # five columns take the wide layout: tunes its SpMM, warms the graph path
-        P3.solve_dev(w3[:5], o3[:5], batched=True, precision=F.FEMH_FP64, rtol=1e-3)
+        # nine columns take the wide layout: tunes its SpMM, warms the graph path
+        P3.solve_dev(w3[:9], o3[:9], batched=True, precision=F.FEMH_FP64, rtol=1e-3)
         torch.cuda.synchronize()
         a = time.perf_counter()
         stats3, st3 = P3.solve_dev(w3, o3, batched=True, precision=F.FEMH_FP64, rtol=1e-6)

@@ -217,7 +217,9 @@ int femh_solve_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* wave
  * opts->inner_rtol (default 1e-3) is the residual drop that triggers a
  * column's update (its true residual replaces the recurrence's).
  * Up to four right-hand sides use a narrow [n_unknowns][4] layout whose
- * product reads each matrix value once for all columns; more use the
+ * product reads each matrix value once for all columns; five to eight run
+ * as two such groups (four and the rest) stepped together, each column's
+ * result identical to solving its group alone; more use the
  * [n_unknowns][64] layout.  Device memory: five complex128 blocks of that
  * layout.  H_out_dev as in femh_solve_dev. */
 int femh_solve_batched_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves,

@@ -150,3 +150,20 @@ def test_pec_sphere_40_b64_full_size(ctx, torch):
         res = solve.residual(A, x, B[:, r])
         assert res <= 1e-6 * 1.001, (r, res, stats[r])
     P.close()
+
+
+def test_mid_size_batch_runs_as_narrow_groups(ctx, torch):
+    """Seven right-hand sides run as a group of four and a group of three:
+    each column is bit-identical to the batched solve of its group alone."""
+    prob, waves = W.pec_sphere_batched(n=12, radius=0.3, nrhs=7, seed=31)
+    P = F.Problem(ctx, prob)
+    out = torch.zeros(P.grid_shape(7), dtype=torch.complex128, device="cuda")
+    stats, st = P.solve_dev(waves, out, batched=True, rtol=1e-8)
+    assert st == F.FEMH_OK, stats
+    for g, k in ((0, 4), (4, 3)):
+        o = torch.zeros(P.grid_shape(k), dtype=torch.complex128, device="cuda")
+        s, st2 = P.solve_dev(waves[g:g + k], o, batched=True, rtol=1e-8)
+        assert st2 == F.FEMH_OK
+        assert torch.equal(o, out[g:g + k])
+        assert [x["iters"] for x in s] == [x["iters"] for x in stats[g:g + k]]
+    P.close()
