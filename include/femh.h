@@ -308,7 +308,7 @@ typedef struct {
                                  batched solve each (as femh_solve_batched_dev: FP64 directions,
                                  the complex128 matrix for FEMH_FP64, else the complex64 one);
                                  0: one single-RHS solve per wave (as femh_solve) */
-  int32_t reserved;           /* 0 */
+  int32_t reserved;           /* must be 0 (FEMH_E_INVALID otherwise) */
 } femh_server_opts;
 
 typedef struct {

@@ -350,8 +350,9 @@ int femh_server_create(femh_ctx* ctx_, const femh_server_opts* opts, femh_server
   *out = nullptr;
   femh_server_opts o{};
   if (opts) o = *opts;
-  if (o.hbm_budget_bytes < 0 || o.max_slots < 0 || o.chunk_iters < 0 || o.batch_rhs < 0 || o.batch_rhs > 1) {
-    femh::set_error("server options must be >= 0 (batch_rhs 0 or 1)");
+  if (o.hbm_budget_bytes < 0 || o.max_slots < 0 || o.chunk_iters < 0 || o.batch_rhs < 0 || o.batch_rhs > 1 ||
+      o.reserved != 0) {
+    femh::set_error("server options must be >= 0 (batch_rhs 0 or 1, reserved 0)");
     return FEMH_E_INVALID;
   }
   FEMH_TRY_HIP(hipSetDevice(ctx->device));
