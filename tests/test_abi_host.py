@@ -188,3 +188,35 @@ def test_null_handles_are_safe(lib):
     lib.femh_problem_destroy(None)
     lib.femh_server_destroy(None)
     assert lib.femh_problem_get_info(None, None) == F.FEMH_E_INVALID
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every public struct of include/femh.h has the size and field offsets
+    the ctypes binding declares (a C program compiled against the header
+    prints them)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = ["femh_allocator", "femh_problem_desc", "femh_plane_wave", "femh_solve_opts", "femh_solve_stats",
+             "femh_problem_info", "femh_server_opts", "femh_server_report"]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "femh.h"', "int main(void) {"]
+    for n in names:
+        cls = getattr(F, n)
+        lines.append(f'  printf("{n} size %zu\\n", sizeof({n}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{n} {fname} %zu\\n", offsetof({n}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for n in names:
+        cls = getattr(F, n)
+        assert got[(n, "size")] == C.sizeof(cls), n
+        for fname, _ in cls._fields_:
+            assert got[(n, fname)] == getattr(cls, fname).offset, (n, fname)
