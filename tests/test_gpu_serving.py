@@ -158,3 +158,30 @@ def test_batch_rhs_requests_same_alone_in_mix_and_batched(ctx, prec):
         for r in range(len(w)):
             assert np.linalg.norm(H[r] - Hs[r]) / np.linalg.norm(Hs[r]) <= 1e-6
         P.close()
+
+
+def test_batch_rhs_cancel_and_admission(ctx):
+    """With batch_rhs, a long batched request can be cancelled while the
+    others finish; under a small memory budget every batched request is
+    still served and the resident bytes (estimates that include the batched
+    groups' workspace) never exceed it."""
+    big, wbig = W.pec_sphere_batched(n=30, radius=0.8, nrhs=3, seed=9)
+    small = [W.serving_request(np.random.default_rng(s), n_lo=8, n_hi=12, nrhs_hi=3) for s in (21, 22, 23)]
+    srv = F.Server(ctx, max_slots=4, chunk_iters=16, batch_rhs=True)
+    tb = srv.submit(big, wbig, precision=F.FEMH_FP64, rtol=1e-10)
+    ts = [srv.submit(p, w, precision=F.FEMH_FP64, rtol=1e-6) for p, w in small]
+    assert srv.cancel(tb) == F.FEMH_OK
+    st, _, _ = srv.poll(tb, 3, None, want_field=False)
+    assert st == F.FEMH_E_CANCELLED
+    for (p, w), t in zip(small, ts):
+        s, _, stats = srv.poll(t, len(w), _shape(p, len(w)))
+        assert s == F.FEMH_OK, stats
+    srv.close()
+    srv = F.Server(ctx, hbm_budget_bytes=96 << 20, max_slots=4, batch_rhs=True)
+    ts = [srv.submit(p, w, precision=F.FEMH_FP64, rtol=1e-6) for p, w in small]
+    for (p, w), t in zip(small, ts):
+        s, _, _ = srv.poll(t, len(w), None, want_field=False)
+        assert s == F.FEMH_OK
+    rep = srv.report()
+    assert rep["peak_resident_bytes"] <= 96 << 20 and rep["completed"] == 3
+    srv.close()
