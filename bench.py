@@ -56,9 +56,9 @@ HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E datasheet
 MEASURED_TRAFFIC = {
     "kernel": "k_cocg_spmv_dot<double>",
     "source": "paper_0704_2344_amd/csrc/krylov_kernels.hip",
-    "sha256": "fc0b2599ba2e7415292bebd8f759ea928734ad7c87a4f3b11786bf941ce86edc",
-    "fetch_kib": 54994.12, "write_kib": 1426.29,
-    "copy_fetch_kib": 524300.59, "copy_write_kib": 1048576.00, "copy_bytes": 1 << 30,
+    "sha256": "793b5cc9825422ffab8d35d4fc7c1e172439c2999798d687d6ada81f8d422948",
+    "fetch_kib": 55009.66, "write_kib": 1426.29,
+    "copy_fetch_kib": 524300.64, "copy_write_kib": 1048576.00, "copy_bytes": 1 << 30,
 }
 
 

@@ -385,17 +385,24 @@ __global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const V
                                                           typename Cx<R>::T* __restrict__ q, const CocgScalars* sc,
                                                           double* __restrict__ partials) {
   using C = typename Cx<R>::T;
-  if (sc->done) return;
+  // the stop flag is read here but tested after the wave's first row, so
+  // its latency hides under that row's loads
+  const int32_t stopped = sc->done;
   const int lane = threadIdx.x & 63;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   int nwaves;
   const int w = wave_row_start(nwaves);
+  bool first = true;
   for (int32_t r0 = w; r0 < pt.nn; r0 += kRowsPerWave * nwaves) {
     int32_t rows[kRowsPerWave];
 #pragma unroll
     for (int k = 0; k < kRowsPerWave; ++k) rows[k] = r0 + k * nwaves;
     R yr[kRowsPerWave], yi[kRowsPerWave];
     rows_product<R, kRowsPerWave, VC>(pt, val, p, rows, lane, yr, yi);
+    if (first) {
+      if (__builtin_amdgcn_readfirstlane(stopped)) return;
+      first = false;
+    }
     if (lane == 0 || lane == 3 || lane == 6) {
 #pragma unroll
       for (int k = 0; k < kRowsPerWave; ++k) {
@@ -413,6 +420,7 @@ __global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const V
       }
     }
   }
+  if (__builtin_amdgcn_readfirstlane(stopped)) return;
   store_partials4(v, partials);
 }
 
@@ -430,7 +438,7 @@ __global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t n, const typenam
                                                         const double* __restrict__ pin, int nin,
                                                         double* __restrict__ pout, int par) {
   using C = typename Cx<R>::T;
-  if (sc->done) return;
+  const int32_t stopped = sc->done;
   const double2 rho = sc->rho[par];
   const double bd_tol = sc->bd_tol;
   const int64_t stride = (int64_t)gridDim.x * kBlock * kPerThread;
@@ -450,6 +458,9 @@ __global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t n, const typenam
     }
   };
   load(i0);
+  // the stop flag is tested after the loads above are issued (it is the
+  // same for the whole grid, so every thread takes the same exit)
+  if (__builtin_amdgcn_readfirstlane(stopped)) return;
   double t[4];
   reduce_partials4(pin, nin, t);
   const double2 pq = make_double2(t[0], t[1]);
@@ -502,7 +513,7 @@ __global__ void __launch_bounds__(kBlock) k_cocg_pupdate(int64_t n, const typena
                                                          typename Cx<R>::T* __restrict__ p, CocgScalars* sc,
                                                          const double* __restrict__ pin, int nin, int par) {
   using C = typename Cx<R>::T;
-  if (sc->done) return;
+  const int32_t stopped = sc->done;
   // operands of the first sweep and the scalars first (as in the update)
   const int it = sc->iters[par] + 1;
   const double rmax = sc->rr_max[par];
@@ -524,6 +535,7 @@ __global__ void __launch_bounds__(kBlock) k_cocg_pupdate(int64_t n, const typena
     }
   };
   load(i0);
+  if (__builtin_amdgcn_readfirstlane(stopped)) return;
   double t[4];
   reduce_partials4(pin, nin, t);
   const double2 rho_new = make_double2(t[0], t[1]);
