@@ -56,9 +56,9 @@ HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E datasheet
 MEASURED_TRAFFIC = {
     "kernel": "k_cocg_spmv_dot<double>",
     "source": "paper_0704_2344_amd/csrc/krylov_kernels.hip",
-    "sha256": "793b5cc9825422ffab8d35d4fc7c1e172439c2999798d687d6ada81f8d422948",
-    "fetch_kib": 55009.66, "write_kib": 1426.29,
-    "copy_fetch_kib": 524300.64, "copy_write_kib": 1048576.00, "copy_bytes": 1 << 30,
+    "sha256": "cbe596e756dd2f79a2e7a694e073f0318da7e3cdbcfdb6d0fb4d2f59920f807e",
+    "fetch_kib": 55019.86, "write_kib": 1426.29,
+    "copy_fetch_kib": 524299.81, "copy_write_kib": 1048576.00, "copy_bytes": 1 << 30,
 }
 
 
@@ -279,7 +279,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "traffic_over_algorithmic": traffic / b128 if traffic else None,
-                     "kernel": "k_cocg_spmv_dot<double> (complex128 block SpMV + p^T A p)",
+                     "kernel": "k_cocg_spmv_dot<double> (complex128 block SpMV w = A z + z^T w)",
                      "bytes_per_launch": b128, "avg_launch_s": avg, "launches": cnt[0],
                      "note": "the 111 MB complex128 matrix fits the 256 MB Infinity Cache"},
     }

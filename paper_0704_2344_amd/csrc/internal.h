@@ -69,7 +69,8 @@ struct PatternDev {
 // iteration (a kernel argument), so no workgroup of a launch can observe a
 // value another workgroup of the same launch writes.  Complex as double2.
 struct CocgScalars {
-  double2 rho[2];      // r^T z of the current iterate, slot = parity
+  double2 rho[2];      // r^T z of the current iterate (single-reduction form: p^T A p of
+                       // the last step), slot = parity
   double2 alpha, beta; // last step (beta also feeds cocg_pupdate_*)
   double rr;           // ||r||^2 after the last iteration (host view)
   double bb;           // ||b||^2 of the system being solved
@@ -216,6 +217,21 @@ hipError_t cocg_update_c128(hipStream_t st, int64_t n, const double2* dinv, doub
                             const void* partials_in, int nin, void* partials_out, int par);
 hipError_t cocg_pupdate_c128(hipStream_t st, int64_t n, const double2* dinv, const double2* r,
                              double2* p, CocgScalars* sc, const void* partials_in, int par);
+// Single-reduction form of the FP64 COCG step: cocg_spmv_dot_c128 on z
+// (w = A z, partials of z^T w) and sr_update_c128 make an iteration.
+// sr_init: z = D^-1 r, p = s = 0, partials of r^T z, z^T s, ||r||^2,
+// ||z||^2 into partials_out (8 values per workgroup, reduce_blocks_for(n)
+// workgroups); slot par marks the first step.  sr_update: the step's scalars
+// from the product's partials (partials_a, nin_a workgroups) and the previous
+// update's or sr_init's (partials_b), then p, s, x, z and the next
+// partials into partials_out, which must be a different buffer (the
+// residual is carried as z; r is not written while iterating).
+hipError_t sr_init_c128(hipStream_t st, int64_t n, const double2* r, const double2* dinv, double2* z,
+                        double2* p, double2* s, CocgScalars* sc, void* partials_out, int par);
+hipError_t sr_update_c128(hipStream_t st, int64_t n, const double2* dinv, double2* x, double2* z,
+                          const double2* w, double2* p, double2* s, CocgScalars* sc,
+                          const void* partials_a, int nin_a, const void* partials_b,
+                          void* partials_out, int par);
 // p = D^-1 r + beta p with beta from the scalar block (after a reliable update)
 hipError_t cocg_apply_beta_c128(hipStream_t st, int64_t n, const double2* dinv, const double2* r,
                                 double2* p, const CocgScalars* sc);

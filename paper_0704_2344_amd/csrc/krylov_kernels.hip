@@ -610,6 +610,238 @@ __global__ void __launch_bounds__(kBlock) k_cocg_apply_beta(int64_t n, const typ
   }
 }
 
+// ---------------------------------------------- single-reduction COCG (FP64)
+// The same Krylov iterates as COCG (section 3.1.5.1), reorganised so that one
+// global reduction per iteration suffices: with z = D^-1 r and w = A z
+// computed first, every scalar of the step follows from dot products of
+// vectors available before the direction is updated:
+//   gamma = r^T z,  delta = z^T w,  mu = z^T s_old          (s = A p)
+//   beta  = -mu / pi_old   (makes p A-conjugate to p_old)
+//   pi    = p^T s = delta + 2 beta mu + beta^2 pi_old       (A = A^T)
+//   alpha = gamma / pi
+//   p = z + beta p,  s = w + beta s,  x += alpha p,  z -= alpha D^-1 s.
+// In exact arithmetic beta equals the COCG ratio of successive r^T z and pi
+// the COCG denominator p^T A p.  Chronopoulos and Gear's single-reduction CG
+// takes the conjugation from that recurrence instead (pi = delta - beta^2
+// pi_old); on these indefinite systems it needs about 11 % more iterations
+// than COCG, the explicit mu a few percent.  The product kernel
+// (k_cocg_spmv_dot on z) yields delta; the update kernel yields gamma, mu,
+// ||r||^2 and ||z||^2 of the next step, since it holds the new s and the new
+// z of each entry.  One product and one update kernel make an iteration.
+// The residual itself is not stored while iterating: the update carries z
+// (the product's input) and forms r = D z entry by entry (D = 1 / D^-1) for
+// r^T z and ||r||^2.
+
+// Per-workgroup partials of 8 sums (gamma re/im, mu re/im, ||r||^2,
+// ||z||^2, 0, 0) -> partials[block][8].
+__device__ __forceinline__ void store_partials8(double (&v)[8], double* __restrict__ partials) {
+  block_sum<double, 8>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) partials[(size_t)blockIdx.x * 8 + i] = v[i];
+  }
+}
+
+// Both partial sets of a step in one pass, each in a fixed order: t[0..3]
+// from the product's na workgroups (4 values each), t[4..11] from the
+// previous update's nb workgroups (8 values each).  All loads of a thread's
+// first producers are issued before any is summed.
+__device__ __forceinline__ void reduce_step_partials(const double* __restrict__ pa, int na,
+                                                     const double* __restrict__ pb, int nb, double (&t)[12]) {
+  __shared__ double s_tot[12];
+  double acc[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = 0.0;
+  const double2* a2 = reinterpret_cast<const double2*>(pa);
+  const double2* b2 = reinterpret_cast<const double2*>(pb);
+  double2 lo[8], hi[8], bq[4];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int b = threadIdx.x + k * kBlock;
+    lo[k] = b < na ? a2[2 * (size_t)b] : make_double2(0.0, 0.0);
+    hi[k] = b < na ? a2[2 * (size_t)b + 1] : make_double2(0.0, 0.0);
+  }
+  const bool has_b = (int)threadIdx.x < nb;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bq[k] = has_b ? b2[4 * (size_t)threadIdx.x + k] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (threadIdx.x + k * kBlock < na) {
+      acc[0] += lo[k].x;
+      acc[1] += lo[k].y;
+      acc[2] += hi[k].x;
+      acc[3] += hi[k].y;
+    }
+  }
+  for (int b = threadIdx.x + 8 * kBlock; b < na; b += kBlock)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += pa[(size_t)b * 4 + i];
+  if (has_b)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      acc[4 + 2 * k] += bq[k].x;
+      acc[5 + 2 * k] += bq[k].y;
+    }
+  for (int b = threadIdx.x + kBlock; b < nb; b += kBlock)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[4 + i] += pb[(size_t)b * 8 + i];
+  block_sum<double, 12>(acc);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) s_tot[i] = acc[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 12; ++i) t[i] = s_tot[i];
+}
+
+// Segment start (r = the residual to restart from): z = D^-1 r, p = s = 0;
+// the update kernel's partials of
+// gamma, mu (= 0), ||r||^2, ||z||^2; pi_old = 0 in slot par marks the first
+// step (beta = 0).  Same workgroup count as the update kernel.
+__global__ void __launch_bounds__(kBlock) k_sr_init(int64_t n, const double2* __restrict__ r,
+                                                    const double2* __restrict__ dinv, double2* __restrict__ z,
+                                                    double2* __restrict__ p, double2* __restrict__ s,
+                                                    CocgScalars* sc, double* __restrict__ pout, int par) {
+  if (sc->done) return;
+  double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double2 ri = r[i], di = dinv[i];
+    const double zr = di.x * ri.x - di.y * ri.y;
+    const double zi = di.x * ri.y + di.y * ri.x;
+    z[i] = make_double2(zr, zi);
+    p[i] = make_double2(0.0, 0.0);
+    s[i] = make_double2(0.0, 0.0);
+    v[0] += ri.x * zr - ri.y * zi;
+    v[1] += ri.x * zi + ri.y * zr;
+    v[4] += ri.x * ri.x + ri.y * ri.y;
+    v[5] += zr * zr + zi * zi;
+  }
+  store_partials8(v, pout);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->iters[par] = sc->iters_out;
+    sc->rho[par] = make_double2(0.0, 0.0);
+  }
+}
+
+// One step: reduce the product's partials (delta) and the previous step's
+// (gamma, mu, ||r||^2, ||z||^2); decide convergence / iteration limit /
+// breakdown identically in every workgroup; otherwise update p, s, x, z
+// and emit the next step's partials.  Slot par holds pi_old and the
+// iteration count; slot par ^ 1 receives pi and the count.  Breakdown:
+// gamma negligible against ||r|| ||z||, or pi lost to cancellation among its
+// three terms (or zero / not finite).
+__global__ void __launch_bounds__(kBlock) k_sr_update(int64_t n, const double2* __restrict__ dinv,
+                                                      double2* __restrict__ x,
+                                                      double2* __restrict__ z, const double2* __restrict__ w,
+                                                      double2* __restrict__ p, double2* __restrict__ s,
+                                                      CocgScalars* sc, const double* __restrict__ pin_a, int nin_a,
+                                                      const double* __restrict__ pin_b, int nin_b,
+                                                      double* __restrict__ pout, int par) {
+  const int32_t stopped = sc->done;
+  const double2 pi_old = sc->rho[par];
+  const int it = sc->iters[par];
+  const double tol2bb = sc->tol2 * sc->bb, bd_tol = sc->bd_tol;
+  const int max_iters = sc->max_iters;
+  const int64_t stride = (int64_t)gridDim.x * kBlock * kPerThread;
+  int64_t i0 = (int64_t)blockIdx.x * kBlock * kPerThread + threadIdx.x;
+  double2 zv[kPerThread], wv[kPerThread], pv[kPerThread], sv[kPerThread], xv[kPerThread], dv[kPerThread];
+  auto load = [&](int64_t b) {
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t i = b + (int64_t)k * kBlock;
+      if (i < n) {
+        zv[k] = z[i];
+        wv[k] = w[i];
+        pv[k] = p[i];
+        sv[k] = s[i];
+        xv[k] = x[i];
+        dv[k] = dinv[i];
+      }
+    }
+  };
+  load(i0);
+  if (__builtin_amdgcn_readfirstlane(stopped)) return;
+  double t[12];
+  reduce_step_partials(pin_a, nin_a, pin_b, nin_b, t);
+  const double2 delta = make_double2(t[0], t[1]);
+  const double2 gamma = make_double2(t[4], t[5]), mu = make_double2(t[6], t[7]);
+  const double rr = t[8], zz = t[9];
+  int stop = 0;
+  double2 beta = make_double2(0.0, 0.0), pi = delta;
+  if (rr <= tol2bb) stop = 1;
+  else if (it >= max_iters) stop = 2;
+  else if (cabs2(gamma) <= bd_tol * bd_tol * rr * zz) stop = 3;
+  if (!stop) {
+    double mag = sqrt(cabs2(delta));
+    if (pi_old.x != 0.0 || pi_old.y != 0.0) {
+      const double2 b = cdiv(mu, pi_old);
+      beta = make_double2(-b.x, -b.y);
+      const double2 bm = make_double2(beta.x * mu.x - beta.y * mu.y, beta.x * mu.y + beta.y * mu.x);
+      const double2 b2 = make_double2(beta.x * beta.x - beta.y * beta.y, 2.0 * beta.x * beta.y);
+      const double2 bbp = make_double2(b2.x * pi_old.x - b2.y * pi_old.y, b2.x * pi_old.y + b2.y * pi_old.x);
+      pi = make_double2(delta.x + 2.0 * bm.x + bbp.x, delta.y + 2.0 * bm.y + bbp.y);
+      mag += 2.0 * sqrt(cabs2(bm)) + sqrt(cabs2(bbp));
+    }
+    if (!(sqrt(cabs2(pi)) > bd_tol * mag)) stop = 3;
+  }
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (stop) {
+    if (lead) {
+      sc->iters[par ^ 1] = it;
+      sc->iters_out = it;
+      sc->rr = rr;
+      sc->stop_par = par;
+      sc->done = stop;
+    }
+    return;
+  }
+  const double2 alpha = cdiv(gamma, pi);
+  if (lead) {
+    sc->rho[par ^ 1] = pi;
+    sc->iters[par ^ 1] = it + 1;
+    sc->iters_out = it + 1;
+    sc->rr = rr;
+    sc->alpha = alpha;
+    sc->beta = beta;
+  }
+  const double ar = alpha.x, ai = alpha.y, br = beta.x, bi = beta.y;
+  double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  while (i0 < n) {
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t i = i0 + (int64_t)k * kBlock;
+      if (i >= n) continue;
+      const double2 zi = zv[k], wi = wv[k], po = pv[k], so = sv[k], di = dv[k];
+      const double2 pn = make_double2(zi.x + br * po.x - bi * po.y, zi.y + br * po.y + bi * po.x);
+      const double2 sn = make_double2(wi.x + br * so.x - bi * so.y, wi.y + br * so.y + bi * so.x);
+      double2 xi = xv[k];
+      xi.x += ar * pn.x - ai * pn.y;
+      xi.y += ar * pn.y + ai * pn.x;
+      // z -= alpha D^-1 s
+      const double2 as = make_double2(ar * sn.x - ai * sn.y, ar * sn.y + ai * sn.x);
+      const double zr = zi.x - (di.x * as.x - di.y * as.y);
+      const double zim = zi.y - (di.x * as.y + di.y * as.x);
+      // r = D z with D = 1 / D^-1
+      const double inv = 1.0 / (di.x * di.x + di.y * di.y);
+      const double2 ri = make_double2((di.x * zr + di.y * zim) * inv, (di.x * zim - di.y * zr) * inv);
+      p[i] = pn;
+      s[i] = sn;
+      x[i] = xi;
+      z[i] = make_double2(zr, zim);
+      v[0] += ri.x * zr - ri.y * zim;
+      v[1] += ri.x * zim + ri.y * zr;
+      v[2] += zr * sn.x - zim * sn.y;
+      v[3] += zr * sn.y + zim * sn.x;
+      v[4] += ri.x * ri.x + ri.y * ri.y;
+      v[5] += zr * zr + zim * zim;
+    }
+    i0 += stride;
+    if (i0 < n) load(i0);
+  }
+  store_partials8(v, pout);
+}
+
 // Reliable update (complex64 recurrence), see the launcher's comment.
 __global__ void __launch_bounds__(kBlock) k_cocg_rescale(int64_t n, const double2* __restrict__ r64, double inv_s,
                                                          const float2* __restrict__ dinv, float2* __restrict__ r,
@@ -828,6 +1060,23 @@ hipError_t cocg_spmv_dot_c128(hipStream_t st, const PatternDev& pt, const double
                               CocgScalars* sc, void* partials, SpmvLaunch L) {
   hipLaunchKernelGGL((k_cocg_spmv_dot<double>), dim3(L.blocks), dim3(kBlock), 0, st, pt, val, p, q, sc,
                      reinterpret_cast<double*>(partials));
+  return hipGetLastError();
+}
+
+hipError_t sr_init_c128(hipStream_t st, int64_t n, const double2* r, const double2* dinv, double2* z, double2* p,
+                        double2* s, CocgScalars* sc, void* partials_out, int par) {
+  hipLaunchKernelGGL(k_sr_init, dim3(reduce_blocks_for(n)), dim3(kBlock), 0, st, n, r, dinv, z, p, s, sc,
+                     reinterpret_cast<double*>(partials_out), par);
+  return hipGetLastError();
+}
+
+hipError_t sr_update_c128(hipStream_t st, int64_t n, const double2* dinv, double2* x, double2* z, const double2* w,
+                          double2* p, double2* s, CocgScalars* sc, const void* partials_a, int nin_a,
+                          const void* partials_b, void* partials_out, int par) {
+  const int nb = reduce_blocks_for(n);
+  hipLaunchKernelGGL(k_sr_update, dim3(nb), dim3(kBlock), 0, st, n, dinv, x, z, w, p, s, sc,
+                     reinterpret_cast<const double*>(partials_a), nin_a,
+                     reinterpret_cast<const double*>(partials_b), nb, reinterpret_cast<double*>(partials_out), par);
   return hipGetLastError();
 }
 

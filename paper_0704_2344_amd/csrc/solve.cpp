@@ -7,9 +7,10 @@
 // asynchronously (pinned memory + event).
 //
 // FP64 mode: COCG with diagonal preconditioning (section 3.1.5.1) on the
-// complex128 matrix; when the recursive residual meets the tolerance the
-// FP64 true residual b - A x is formed and, if it does not meet it, COCG
-// restarts from it.
+// complex128 matrix, in its single-reduction form (one product and one
+// update kernel per iteration, see sr_update_c128); when the recursive
+// residual meets the tolerance the FP64 true residual b - A x is formed and,
+// if it does not meet it, COCG restarts from it.
 //
 // Matrix-mixed mode: the FP64 COCG recurrence with the complex64 matrix in
 // the product (values promoted, FP64 sums); reliable updates against the
@@ -65,13 +66,17 @@ struct Stepper {
   femh_solve_opts o{};
   bool mixed = false;  // complex64 vectors and matrix
   bool m32 = false;    // complex64 matrix, complex128 vectors
+  bool sr = false;     // FP64: single-reduction recurrence
   int64_t n = 0;
   std::vector<void*> owned;
   // device workspace
   double2 *r64 = nullptr, *p64 = nullptr, *q64 = nullptr;
+  double2 *z64 = nullptr, *s64 = nullptr;  // single-reduction form: z = D^-1 r, s = A p (q64 holds A z)
   float2 *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
   void* partials = nullptr;  // SpMV -> update partials; also once-per-segment kernels
-  void* partials_b = nullptr;  // update -> direction-update partials
+  void* partials_b = nullptr;  // update -> direction-update partials (single-reduction form:
+                               // two buffers of 8 values per workgroup, update -> next
+                               // update, by parity)
   CocgScalars* sc = nullptr;
   Aux* aux = nullptr;
   const double2* dinv64 = nullptr;
@@ -129,6 +134,7 @@ struct Stepper {
     o = opts;
     mixed = o.precision == FEMH_MIXED;
     m32 = o.precision == FEMH_MIXED_MATRIX;
+    sr = !mixed && !m32;
     n = 3 * (int64_t)P->pat.nn;
     r64 = (double2*)dev(16 * n);
     if (!r64) return oom();
@@ -142,9 +148,14 @@ struct Stepper {
       p64 = (double2*)dev(16 * n);
       q64 = (double2*)dev(16 * n);
       if (!p64 || !q64) return oom();
+      if (sr) {
+        z64 = (double2*)dev(16 * n);
+        s64 = (double2*)dev(16 * n);
+        if (!z64 || !s64) return oom();
+      }
     }
     partials = dev(8 * kPartialSlots);
-    partials_b = dev(8 * kPartialSlots);
+    partials_b = dev(8 * kPartialSlots * (sr ? 4 : 1));
     sc = (CocgScalars*)dev(sizeof(CocgScalars));
     aux = (Aux*)dev(sizeof(Aux));
     if (!partials || !partials_b || !sc || !aux) return oom();
@@ -180,6 +191,14 @@ struct Stepper {
   }
 
   double* dpart() { return reinterpret_cast<double*>(partials); }
+  // single-reduction form: two buffers of 2048 workgroups x 8 values
+  void* bpart(int slot) { return reinterpret_cast<double*>(partials_b) + (size_t)slot * 2 * kPartialSlots; }
+
+  // single-reduction segment start from the residual in r64
+  int queue_sr_init() {
+    FEMH_TRY_HIP(k::sr_init_c128(s, n, r64, dinv64, z64, p64, s64, sc, bpart(par()), par()));
+    return FEMH_OK;
+  }
 
   // ---- queue helpers
   int queue_residual() {
@@ -210,11 +229,13 @@ struct Stepper {
       if (prof) FEMH_TRY_HIP(hipEventRecord(e1, s));
       FEMH_TRY_HIP(k::cocg_update_c64(s, n, dinv32, x32, r32, p32, q32, sc, partials, nin, partials_b, pr));
       FEMH_TRY_HIP(k::cocg_pupdate_c64(s, n, dinv32, r32, p32, sc, partials_b, pr));
+    } else if (sr) {
+      FEMH_TRY_HIP(k::cocg_spmv_dot_c128(s, P->pat, P->val64, z64, q64, sc, partials, P->spmv));
+      if (prof) FEMH_TRY_HIP(hipEventRecord(e1, s));
+      FEMH_TRY_HIP(k::sr_update_c128(s, n, dinv64, x, z64, q64, p64, s64, sc, partials, nin, bpart(pr),
+                                     bpart(pr ^ 1), pr));
     } else {
-      if (m32)
-        FEMH_TRY_HIP(k::cocg_spmv_dot_m32(s, P->pat, P->val32, p64, q64, sc, partials, P->spmv));
-      else
-        FEMH_TRY_HIP(k::cocg_spmv_dot_c128(s, P->pat, P->val64, p64, q64, sc, partials, P->spmv));
+      FEMH_TRY_HIP(k::cocg_spmv_dot_m32(s, P->pat, P->val32, p64, q64, sc, partials, P->spmv));
       if (prof) FEMH_TRY_HIP(hipEventRecord(e1, s));
       FEMH_TRY_HIP(k::cocg_update_c128(s, n, dinv64, x, r64, p64, q64, sc, partials, nin, partials_b, pr));
       FEMH_TRY_HIP(k::cocg_pupdate_c128(s, n, dinv64, r64, p64, sc, partials_b, pr));
@@ -243,7 +264,9 @@ struct Stepper {
 
   void collect_profile(int iters_now) {
     if (!c->profile) return;
-    const int real = iters_now - seg_iters;
+    // the single-reduction form runs one more full product than updates
+    // (the step that stops does so after its product)
+    const int real = std::min(iters_now - seg_iters + (sr ? 1 : 0), launches - seg_first);
     (void)hipStreamSynchronize(s);
     for (int i = 0; i < real; ++i) {
       float ms = 0.f;
@@ -281,7 +304,8 @@ struct Stepper {
       hw->bd_tol = 1e-14;
       if (m32) hw->delta2 = o.inner_rtol * o.inner_rtol;
       FEMH_TRY_HIP(hipMemcpyAsync(sc, hw, sizeof(*hw), hipMemcpyHostToDevice, s));
-      FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, partials, 0, par()));
+      if (sr) FEMH_TRY(queue_sr_init());
+      else FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, partials, 0, par()));
     }
     new_segment(0);
     return FEMH_OK;
@@ -328,7 +352,8 @@ struct Stepper {
       hw->iters_out = iters;
       if (m32) hw->delta2 = o.inner_rtol * o.inner_rtol;
       FEMH_TRY_HIP(hipMemcpyAsync(sc, hw, sizeof(*hw), hipMemcpyHostToDevice, s));
-      FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, partials, 0, par()));
+      if (sr) FEMH_TRY(queue_sr_init());
+      else FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, partials, 0, par()));
     }
     new_segment(iters);
     return FEMH_OK;
