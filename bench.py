@@ -56,9 +56,9 @@ HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E datasheet
 MEASURED_TRAFFIC = {
     "kernel": "k_cocg_spmv_dot<double>",
     "source": "paper_0704_2344_amd/csrc/krylov_kernels.hip",
-    "sha256": "cbe596e756dd2f79a2e7a694e073f0318da7e3cdbcfdb6d0fb4d2f59920f807e",
-    "fetch_kib": 55019.86, "write_kib": 1426.29,
-    "copy_fetch_kib": 524299.81, "copy_write_kib": 1048576.00, "copy_bytes": 1 << 30,
+    "sha256": "e45f4058aef0e928736d4c61f92d9825278a531b348be768347a21157c835c02",
+    "fetch_kib": 55020.19, "write_kib": 1426.30,
+    "copy_fetch_kib": 524299.72, "copy_write_kib": 1048576.06, "copy_bytes": 1 << 30,
 }
 
 

@@ -240,6 +240,82 @@ __device__ __forceinline__ void block_sum(R (&v)[NV]) {
   __syncthreads();
 }
 
+// Workgroup sum of eight values, every thread returning with all eight
+// totals.  Within a wave the sums are a reduce-scatter: at lane distance 32
+// each lane keeps half of the values and adds its partner's copy of that
+// half, then a quarter at 16 and one value at 8, so after distances 4, 2, 1
+// lane l holds the wave total of value l >> 3 (10 cross-lane moves for all
+// eight values, against 6 per value for a butterfly on each).  The order of
+// additions depends on lane and wave indices only, so every workgroup forms
+// bit-identical totals from identical inputs.
+__device__ __forceinline__ void block_sum8(double (&v)[8]) {
+  __shared__ double s_w[kBlock / 64][8];
+  __shared__ double s_t[8];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+  double a[4], c[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double give = h32 ? v[i] : v[i + 4];
+    const double keep = h32 ? v[i + 4] : v[i];
+    a[i] = keep + __shfl_xor(give, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double give = h16 ? a[i] : a[i + 2];
+    const double keep = h16 ? a[i + 2] : a[i];
+    c[i] = keep + __shfl_xor(give, 16, 64);
+  }
+  double e = (h8 ? c[1] : c[0]) + __shfl_xor(h8 ? c[0] : c[1], 8, 64);
+  e += __shfl_xor(e, 4, 64);
+  e += __shfl_xor(e, 2, 64);
+  e += __shfl_xor(e, 1, 64);
+  if ((lane & 7) == 0) s_w[wid][lane >> 3] = e;
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    double t = s_w[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) t += s_w[w][threadIdx.x];
+    s_t[threadIdx.x] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = s_t[i];
+}
+
+// The same for four values: at lane distance 32 each lane keeps two, at 16
+// one, so after distances 8, 4, 2, 1 lane l holds the wave total of value
+// (l >> 4) & 3 (7 cross-lane moves, against 24).
+__device__ __forceinline__ void block_sum4(double (&v)[4]) {
+  __shared__ double s_w[kBlock / 64][4];
+  __shared__ double s_t[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const bool h32 = lane & 32, h16 = lane & 16;
+  double a[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double give = h32 ? v[i] : v[i + 2];
+    const double keep = h32 ? v[i + 2] : v[i];
+    a[i] = keep + __shfl_xor(give, 32, 64);
+  }
+  double e = (h16 ? a[1] : a[0]) + __shfl_xor(h16 ? a[0] : a[1], 16, 64);
+  e += __shfl_xor(e, 8, 64);
+  e += __shfl_xor(e, 4, 64);
+  e += __shfl_xor(e, 2, 64);
+  e += __shfl_xor(e, 1, 64);
+  if ((lane & 15) == 0) s_w[wid][lane >> 4] = e;
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = s_w[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) t += s_w[w][threadIdx.x];
+    s_t[threadIdx.x] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = s_t[i];
+}
+
 // Publish this workgroup's NV partial sums; returns true in every thread of
 // the last workgroup to arrive, whose v[] (all threads) then holds the
 // fixed-order total over all workgroups.
@@ -291,7 +367,7 @@ __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.
 // Per-workgroup partials of 4 sums -> partials[block][4] (plain stores; the
 // consumer is a later kernel).
 __device__ __forceinline__ void store_partials4(double (&v)[4], double* __restrict__ partials) {
-  block_sum<double, 4>(v);
+  block_sum4(v);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) partials[(size_t)blockIdx.x * 4 + i] = v[i];
@@ -303,7 +379,6 @@ __device__ __forceinline__ void store_partials4(double (&v)[4], double* __restri
 // have at most 2048 workgroups: a thread's (up to) eight loads are issued
 // together, then summed in order.
 __device__ __forceinline__ void reduce_partials4(const double* __restrict__ partials, int nin, double (&t)[4]) {
-  __shared__ double s_tot[4];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double2 lo[8], hi[8];
   const double2* p2 = reinterpret_cast<const double2*>(partials);
@@ -325,13 +400,9 @@ __device__ __forceinline__ void reduce_partials4(const double* __restrict__ part
   for (int b = threadIdx.x + 8 * kBlock; b < nin; b += kBlock)
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] += partials[(size_t)b * 4 + i];
-  block_sum<double, 4>(acc);
-  if (threadIdx.x == 0)
+  block_sum4(acc);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s_tot[i] = acc[i];
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 4; ++i) t[i] = s_tot[i];
+  for (int i = 0; i < 4; ++i) t[i] = acc[i];
 }
 
 // Segment start: r = src (optionally x = 0), p = D^-1 r; rho = r^T p into
@@ -635,63 +706,54 @@ __global__ void __launch_bounds__(kBlock) k_cocg_apply_beta(int64_t n, const typ
 // Per-workgroup partials of 8 sums (gamma re/im, mu re/im, ||r||^2,
 // ||z||^2, 0, 0) -> partials[block][8].
 __device__ __forceinline__ void store_partials8(double (&v)[8], double* __restrict__ partials) {
-  block_sum<double, 8>(v);
+  block_sum8(v);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) partials[(size_t)blockIdx.x * 8 + i] = v[i];
   }
 }
 
-// Both partial sets of a step in one pass, each in a fixed order: t[0..3]
-// from the product's na workgroups (4 values each), t[4..11] from the
-// previous update's nb workgroups (8 values each).  All loads of a thread's
-// first producers are issued before any is summed.
+// The sums a step needs, each in a fixed order: t[0..1] = z^T w from the
+// product's na workgroups (the first two of its four values; its norms are
+// not needed here), t[2..7] = gamma, mu, ||r||^2, ||z||^2 from the previous
+// update's nb workgroups (eight values each, the last two unused).  All
+// loads of a thread's first producers are issued before any is summed.
 __device__ __forceinline__ void reduce_step_partials(const double* __restrict__ pa, int na,
-                                                     const double* __restrict__ pb, int nb, double (&t)[12]) {
-  __shared__ double s_tot[12];
-  double acc[12];
+                                                     const double* __restrict__ pb, int nb, double (&t)[8]) {
 #pragma unroll
-  for (int i = 0; i < 12; ++i) acc[i] = 0.0;
+  for (int i = 0; i < 8; ++i) t[i] = 0.0;
   const double2* a2 = reinterpret_cast<const double2*>(pa);
   const double2* b2 = reinterpret_cast<const double2*>(pb);
-  double2 lo[8], hi[8], bq[4];
+  double2 da[8], bq[3];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int b = threadIdx.x + k * kBlock;
-    lo[k] = b < na ? a2[2 * (size_t)b] : make_double2(0.0, 0.0);
-    hi[k] = b < na ? a2[2 * (size_t)b + 1] : make_double2(0.0, 0.0);
+    da[k] = b < na ? a2[2 * (size_t)b] : make_double2(0.0, 0.0);
   }
   const bool has_b = (int)threadIdx.x < nb;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) bq[k] = has_b ? b2[4 * (size_t)threadIdx.x + k] : make_double2(0.0, 0.0);
+  for (int k = 0; k < 3; ++k) bq[k] = has_b ? b2[4 * (size_t)threadIdx.x + k] : make_double2(0.0, 0.0);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     if (threadIdx.x + k * kBlock < na) {
-      acc[0] += lo[k].x;
-      acc[1] += lo[k].y;
-      acc[2] += hi[k].x;
-      acc[3] += hi[k].y;
+      t[0] += da[k].x;
+      t[1] += da[k].y;
     }
   }
-  for (int b = threadIdx.x + 8 * kBlock; b < na; b += kBlock)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] += pa[(size_t)b * 4 + i];
+  for (int b = threadIdx.x + 8 * kBlock; b < na; b += kBlock) {
+    t[0] += pa[(size_t)b * 4];
+    t[1] += pa[(size_t)b * 4 + 1];
+  }
   if (has_b)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      acc[4 + 2 * k] += bq[k].x;
-      acc[5 + 2 * k] += bq[k].y;
+    for (int k = 0; k < 3; ++k) {
+      t[2 + 2 * k] += bq[k].x;
+      t[3 + 2 * k] += bq[k].y;
     }
   for (int b = threadIdx.x + kBlock; b < nb; b += kBlock)
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[4 + i] += pb[(size_t)b * 8 + i];
-  block_sum<double, 12>(acc);
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int i = 0; i < 12; ++i) s_tot[i] = acc[i];
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 12; ++i) t[i] = s_tot[i];
+    for (int i = 0; i < 6; ++i) t[2 + i] += pb[(size_t)b * 8 + i];
+  block_sum8(t);
 }
 
 // Segment start (r = the residual to restart from): z = D^-1 r, p = s = 0;
@@ -762,11 +824,11 @@ __global__ void __launch_bounds__(kBlock) k_sr_update(int64_t n, const double2* 
   };
   load(i0);
   if (__builtin_amdgcn_readfirstlane(stopped)) return;
-  double t[12];
+  double t[8];
   reduce_step_partials(pin_a, nin_a, pin_b, nin_b, t);
   const double2 delta = make_double2(t[0], t[1]);
-  const double2 gamma = make_double2(t[4], t[5]), mu = make_double2(t[6], t[7]);
-  const double rr = t[8], zz = t[9];
+  const double2 gamma = make_double2(t[2], t[3]), mu = make_double2(t[4], t[5]);
+  const double rr = t[6], zz = t[7];
   int stop = 0;
   double2 beta = make_double2(0.0, 0.0), pi = delta;
   if (rr <= tol2bb) stop = 1;
