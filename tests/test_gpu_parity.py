@@ -259,6 +259,26 @@ def test_solve_is_deterministic(ctx):
     P.close()
 
 
+@pytest.mark.parametrize("prec", [F.FEMH_FP64, F.FEMH_MIXED_MATRIX])
+def test_chunking_does_not_change_the_solve(ctx, prec):
+    """The host queues iterations in chunks of check_every and keeps two
+    chunks in flight; the scalar slots alternate by launch parity and the
+    launches queued past a stop return at once.  None of that may change the
+    arithmetic: the same solve with chunks of 1, 7 and 32 iterations gives
+    bit-identical fields and the same iteration counts (restarts and
+    reliable updates included)."""
+    prob, waves = CASES["sphere_shell_14"]
+    P = F.Problem(ctx, prob)
+    runs = [P.solve(waves, precision=prec, rtol=1e-10, check_every=ce) for ce in (1, 7, 32)]
+    for H, stats, st in runs:
+        assert st == F.FEMH_OK
+    for H, stats, _ in runs[1:]:
+        np.testing.assert_array_equal(H, runs[0][0])
+        assert [s["iters"] for s in stats] == [s["iters"] for s in runs[0][1]]
+        assert [s["outer_iters"] for s in stats] == [s["outer_iters"] for s in runs[0][1]]
+    P.close()
+
+
 def test_iteration_limit_reports_not_converged(ctx):
     prob, waves = CASES["free_cube_10"]
     P = F.Problem(ctx, prob)
