@@ -227,12 +227,16 @@ int64_t estimate_bytes(const femh_problem_desc* d, int32_t nrhs, int32_t precisi
   b += al(4 * ng) + 3 * al(4 * nn) + al(4 * (nn + 1)) + al(4 * nnzb);
   b += al(144 * nnzb) + al(72 * nnzb) + al(48 * nn) + al(24 * nn);
   // per right-hand side: b and x (FP64), the solver's workspace (mixed: an
-  // FP64 residual and four complex64 vectors; FP64: three FP64 vectors), the
-  // scalar block and partial sums, and the output grid
+  // FP64 residual and four complex64 vectors; matrix-mixed: three FP64
+  // vectors; FP64, in its single-reduction form: five), the partial-sum
+  // buffers of 2048 workgroups x 4 doubles (FP64: five, two otherwise), the
+  // scalar blocks, and the output grid
   const int64_t v64 = al(48 * nn), v32 = al(24 * nn);
   if (nrhs > 0) {
-    const int64_t ws = precision == FEMH_MIXED ? v64 + 4 * v32 : 3 * v64;
-    b += (int64_t)nrhs * (2 * v64 + ws + (1 << 16)) + al((int64_t)nrhs * 48 * ng);
+    const bool fp64 = precision == FEMH_FP64;
+    const int64_t ws = precision == FEMH_MIXED ? v64 + 4 * v32 : (fp64 ? 5 : 3) * v64;
+    const int64_t part = (fp64 ? 5 : 2) * al(8 * 2048 * 4) + 2 * al(1024);
+    b += (int64_t)nrhs * (2 * v64 + ws + part) + al((int64_t)nrhs * 48 * ng);
   }
   b += 1 << 20;  // numbering scratch, scalars
   return b;

@@ -169,7 +169,26 @@ def test_footprint_estimate_grows_with_rhs_and_precision(lib):
     e1 = _estimate(lib, p, 1, F.FEMH_FP64)
     e4 = _estimate(lib, p, 4, F.FEMH_FP64)
     em = _estimate(lib, p, 1, F.FEMH_MIXED)
-    assert e4 > e1 and em > e1 - 5 * 48 * 1331
+    # the mixed form's workspace (an FP64 residual, four complex64 vectors)
+    # is three complex128 vectors, two fewer than FP64's, and it has three
+    # fewer partial buffers
+    v64 = (48 * 1331 + 255) // 256 * 256
+    assert e4 > e1 and em >= e1 - 2 * v64 - 3 * 8 * 2048 * 4
+
+
+def test_footprint_estimate_per_rhs_workspace(lib):
+    """Per right-hand side the FP64 solver (single-reduction form) holds two
+    more complex128 vectors (z = D^-1 r and s = A p) and three more partial
+    buffers (two update buffers of 2048 x 8 doubles) than the matrix-mixed
+    one, which keeps the textbook order."""
+    p, _ = W.free_cube(10)
+    nn = 1331
+    v64 = (48 * nn + 255) // 256 * 256
+    per = {}
+    for prec in (F.FEMH_FP64, F.FEMH_MIXED_MATRIX):
+        per[prec] = _estimate(lib, p, 3, prec) - _estimate(lib, p, 2, prec)
+    d = per[F.FEMH_FP64] - per[F.FEMH_MIXED_MATRIX]
+    assert d == 2 * v64 + 3 * 8 * 2048 * 4
 
 
 def test_context_without_gpu_reports_device_error(lib):
