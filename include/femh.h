@@ -288,12 +288,13 @@ int femh_spmm_set_tile(femh_problem* prob, int32_t kind, int32_t blocks);
  * The denominator for achieved-bandwidth figures. */
 int femh_bw_probe(femh_ctx* ctx, int64_t bytes, int32_t reps, double* gbps);
 
-/* Per-kernel event timing of the solvers.  When enabled, every solve
- * records HIP events around each matrix product it launches; the totals
- * accumulate until read.  spmv_seconds / spmv_launches receive the sum of
- * kernel times and the number of products that did work, per kind (index
- * 0 = FP64, 1 = complex64, 2 = batched SpMM, 3 = complex64 matrix with
- * complex128 vectors). */
+/* Per-kernel event timing of the single-RHS solvers.  When enabled, every
+ * solve records HIP events around every eighth matrix product it launches
+ * (a sample, so that the events barely slow the solve being measured); the
+ * totals accumulate until read.  spmv_seconds / spmv_launches receive the
+ * sum of kernel times and the number of timed products that did work, per
+ * kind (index 0 = FP64, 1 = complex64, 3 = complex64 matrix with complex128
+ * vectors; index 2 stays 0: the batched SpMM is timed by femh_spmm_dev). */
 int femh_profile_enable(femh_ctx* ctx, int32_t on);
 int femh_profile_read(femh_ctx* ctx, double spmv_seconds[4], int64_t spmv_launches[4],
                       int32_t reset);

@@ -35,6 +35,10 @@ namespace femh {
 namespace {
 
 constexpr int kPartialSlots = 2048 * 4;  // partial sums: workgroups x 4 values
+// With profiling on, every kProfStride-th product of a solve is bracketed
+// with events (a sample: each pair of events adds about 2 us to its
+// iteration, so bracketing them all would slow the solve being measured).
+constexpr int kProfStride = 8;
 
 // Device-side auxiliary scalars used outside the COCG block.
 struct Aux {
@@ -211,13 +215,13 @@ struct Stepper {
   int par() const { return launches & 1; }
 
   int queue_iteration() {
-    const bool prof = c->profile;
+    const bool prof = c->profile && launches % kProfStride == 0;
     const int pr = par();
     const int nin = P->spmv.blocks;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
-      e0 = pool_event(c, 2 * (size_t)launches);
-      e1 = pool_event(c, 2 * (size_t)launches + 1);
+      e0 = pool_event(c, 2 * (size_t)(launches / kProfStride));
+      e1 = pool_event(c, 2 * (size_t)(launches / kProfStride) + 1);
       if (!e0 || !e1) {
         set_error("hipEventCreate failed");
         return FEMH_E_DEVICE;
@@ -269,12 +273,15 @@ struct Stepper {
     const int real = std::min(iters_now - seg_iters + (sr ? 1 : 0), launches - seg_first);
     (void)hipStreamSynchronize(s);
     for (int i = 0; i < real; ++i) {
+      const int l = seg_first + i;
+      if (l % kProfStride) continue;
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, c->ev_pool[2 * (size_t)(seg_first + i)],
-                              c->ev_pool[2 * (size_t)(seg_first + i) + 1]) == hipSuccess)
+      if (hipEventElapsedTime(&ms, c->ev_pool[2 * (size_t)(l / kProfStride)],
+                              c->ev_pool[2 * (size_t)(l / kProfStride) + 1]) == hipSuccess) {
         prof_seconds += ms * 1e-3;
+        ++prof_count;
+      }
     }
-    prof_count += real;
   }
 
   // ---- phases
