@@ -279,6 +279,30 @@ def test_chunking_does_not_change_the_solve(ctx, prec):
     P.close()
 
 
+def test_profile_samples_every_eighth_product(ctx):
+    """Event timing brackets every eighth product of a single-RHS solve:
+    the counters report that many timed products, at a plausible per-kernel
+    time, and the sampling leaves the solve itself unchanged."""
+    prob, waves = CASES["sphere_shell_14"]
+    P = F.Problem(ctx, prob)
+    H0, s0, _ = P.solve(waves[:1], precision=F.FEMH_FP64, rtol=1e-10)
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    H1, s1, st = P.solve(waves[:1], precision=F.FEMH_FP64, rtol=1e-10)
+    sec, cnt = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    assert st == F.FEMH_OK
+    np.testing.assert_array_equal(H1, H0)
+    it, seg = s1[0]["iters"], s1[0]["outer_iters"] + 1
+    # products that did work: one per step plus, per segment, the one whose
+    # step stopped; launch k (counted over the solve) is timed when k % 8 == 0
+    assert it > 50
+    assert max(it // 8 - seg, 1) <= cnt[0] <= (it + seg) // 8 + seg
+    assert 1e-6 < sec[0] / cnt[0] < 1e-3
+    assert cnt[1] == 0 and cnt[3] == 0
+    P.close()
+
+
 def test_iteration_limit_reports_not_converged(ctx):
     prob, waves = CASES["free_cube_10"]
     P = F.Problem(ctx, prob)
