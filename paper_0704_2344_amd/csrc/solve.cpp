@@ -102,7 +102,11 @@ struct Stepper {
   int iters = 0;
   int status = FEMH_E_NOT_CONVERGED;
   int last_done = 0;
-  // profiling: launch numbering of the current segment
+  // profiling: launch numbering of the current segment.  Only the
+  // single-solve driver turns timing on: the context's event pool is indexed
+  // by this stepper's launch count, so steppers running concurrently (the
+  // server's) must not record into it.
+  bool timing = false;
   int launches = 0, seg_first = 0, seg_iters = 0;
   double prof_seconds = 0.0;
   int64_t prof_count = 0;
@@ -215,7 +219,7 @@ struct Stepper {
   int par() const { return launches & 1; }
 
   int queue_iteration() {
-    const bool prof = c->profile && launches % kProfStride == 0;
+    const bool prof = timing && launches % kProfStride == 0;
     const int pr = par();
     const int nin = P->spmv.blocks;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -267,7 +271,7 @@ struct Stepper {
   }
 
   void collect_profile(int iters_now) {
-    if (!c->profile) return;
+    if (!timing) return;
     // the single-reduction form runs one more full product than updates
     // (the step that stops does so after its product)
     const int real = std::min(iters_now - seg_iters + (sr ? 1 : 0), launches - seg_first);
@@ -459,6 +463,7 @@ int solve_single(Problem* P, const double2* b, double2* x, const femh_solve_opts
     (void)hipEventDestroy(e1);
     return FEMH_E_OOM;
   }
+  S->timing = c->profile;
   int rc = FEMH_OK;
   while (!stepper_done(S)) {
     bool progress = false;
@@ -478,7 +483,7 @@ int solve_single(Problem* P, const double2* b, double2* x, const femh_solve_opts
   }
   S->fill_stats(st);
   st->seconds = ms * 1e-3;
-  if (c->profile) {
+  if (S->timing) {
     const int slot = S->mixed ? 1 : (S->m32 ? 3 : 0);
     c->prof_sec[slot] += S->prof_seconds;
     c->prof_cnt[slot] += S->prof_count;
