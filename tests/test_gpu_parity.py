@@ -260,6 +260,25 @@ def test_solve_is_deterministic(ctx):
 
 
 @pytest.mark.parametrize("prec", [F.FEMH_FP64, F.FEMH_MIXED_MATRIX])
+@pytest.mark.parametrize("name", ["random_pec_lossy", "mirror_cut_xy"])
+def test_unpreconditioned_solve_matches_lu(ctx, name, prec):
+    """Without Jacobi (D^-1 = 1, so the FP64 recurrence's r = D z is z
+    itself) the solve still reaches the LU solution."""
+    prob, waves = CASES[name]
+    A, B, X = _lu_solution(prob, waves)
+    kappa = float(abs(np.linalg.cond(A.toarray(), 1)))
+    rtol = min(1e-10, 0.1 * 1e-9 / kappa)
+    P = F.Problem(ctx, prob)
+    H, stats, st = P.solve(waves, precision=prec, rtol=rtol, precond=F.FEMH_PRECOND_NONE)
+    assert st == F.FEMH_OK, stats
+    Ho = fem.scatter_to_grid(prob, X)
+    for r in range(len(waves)):
+        assert np.linalg.norm(H[r] - Ho[r]) <= 1e-9 * np.linalg.norm(Ho[r]), (r, stats[r])
+        assert stats[r]["rel_residual"] <= rtol
+    P.close()
+
+
+@pytest.mark.parametrize("prec", [F.FEMH_FP64, F.FEMH_MIXED_MATRIX])
 def test_chunking_does_not_change_the_solve(ctx, prec):
     """The host queues iterations in chunks of check_every and keeps two
     chunks in flight; the scalar slots alternate by launch parity and the
