@@ -56,9 +56,9 @@ HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E datasheet
 MEASURED_TRAFFIC = {
     "kernel": "k_cocg_spmv_dot<double>",
     "source": "paper_0704_2344_amd/csrc/krylov_kernels.hip",
-    "sha256": "e45f4058aef0e928736d4c61f92d9825278a531b348be768347a21157c835c02",
-    "fetch_kib": 55020.19, "write_kib": 1426.30,
-    "copy_fetch_kib": 524299.72, "copy_write_kib": 1048576.06, "copy_bytes": 1 << 30,
+    "sha256": "cd072f4a672b6d11d9031dc700142d67d72c97f56a7b1106968b4250634fdad5",
+    "fetch_kib": 55018.17, "write_kib": 1426.30,
+    "copy_fetch_kib": 524299.84, "copy_write_kib": 1048576.03, "copy_bytes": 1 << 30,
 }
 
 

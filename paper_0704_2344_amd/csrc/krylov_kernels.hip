@@ -456,8 +456,9 @@ __global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const V
                                                           typename Cx<R>::T* __restrict__ q, const CocgScalars* sc,
                                                           double* __restrict__ partials) {
   using C = typename Cx<R>::T;
-  // the stop flag is read here but tested after the wave's first row, so
-  // its latency hides under that row's loads
+  // the stop flag is read here and tested together with the first row's
+  // bounds, a scalar load the row has to wait for anyway, so launches queued
+  // past convergence end before loading a row and working ones wait no longer
   const int32_t stopped = sc->done;
   const int lane = threadIdx.x & 63;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -469,11 +470,12 @@ __global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const V
 #pragma unroll
     for (int k = 0; k < kRowsPerWave; ++k) rows[k] = r0 + k * nwaves;
     R yr[kRowsPerWave], yi[kRowsPerWave];
-    rows_product<R, kRowsPerWave, VC>(pt, val, p, rows, lane, yr, yi);
     if (first) {
-      if (__builtin_amdgcn_readfirstlane(stopped)) return;
+      const int32_t b0 = __builtin_amdgcn_readfirstlane(pt.row_ptr[rows[0]]);
+      if (__builtin_amdgcn_readfirstlane(stopped) && b0 >= 0) return;
       first = false;
     }
+    rows_product<R, kRowsPerWave, VC>(pt, val, p, rows, lane, yr, yi);
     if (lane == 0 || lane == 3 || lane == 6) {
 #pragma unroll
       for (int k = 0; k < kRowsPerWave; ++k) {
