@@ -1,0 +1,63 @@
+"""Host-side checks of the benchmark's bookkeeping (CPU).
+
+The roofline's algorithmic bytes must count every datum of one block
+product once, from the pattern the oracle builds; the HBM-traffic figure
+is the counters scaled by the copy probe's known bytes; a multi-GPU request
+is refused before any device work.
+"""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_spmv_bytes_counts_each_datum_once():
+    """Headline workload: 3x3 complex128 blocks + int32 column index per
+    block, int32 row pointers, one complex128 x read and y written per
+    unknown, counted from the oracle's block pattern."""
+    p, _ = W.pec_cube(30)
+    rp, ci = fem.block_pattern(p)
+    nn, nnzb = len(rp) - 1, len(ci)
+    by_parts = (nnzb * 9 * 16          # block values
+                + ci.size * 4           # column indices
+                + rp.size * 4           # row pointers
+                + 3 * nn * 16           # x
+                + 3 * nn * 16)          # y
+    assert bench.spmv_bytes(nn, nnzb, 16, 16) == by_parts == 110825140
+
+
+def test_spmm_bytes_reduces_to_spmv_for_one_column():
+    p, _ = W.free_cube(6)
+    rp, ci = fem.block_pattern(p)
+    nn, nnzb = len(rp) - 1, len(ci)
+    assert bench.spmm_bytes(nn, nnzb, 1) == bench.spmv_bytes(nn, nnzb, 16, 16)
+
+
+def test_traffic_is_counters_scaled_by_the_copy_probe():
+    m = bench.MEASURED_TRAFFIC
+    t = bench.measured_traffic()
+    if t is None:
+        pytest.skip("kernel source changed since the counters were taken")
+    fetch = m["fetch_kib"] * 1024 * m["copy_bytes"] / (m["copy_fetch_kib"] * 1024)
+    write = m["write_kib"] * 1024 * m["copy_bytes"] / (m["copy_write_kib"] * 1024)
+    assert t == pytest.approx(fetch + write, rel=1e-12)
+    # the copy probe reads and writes 1 GiB: FETCH_SIZE counts half the bytes
+    # read on this part, WRITE_SIZE all bytes written
+    assert m["copy_bytes"] / (m["copy_fetch_kib"] * 1024) == pytest.approx(2.0, rel=1e-3)
+    assert m["copy_bytes"] / (m["copy_write_kib"] * 1024) == pytest.approx(1.0, rel=1e-3)
+
+
+def test_multi_gpu_request_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
