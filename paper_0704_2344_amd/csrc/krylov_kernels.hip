@@ -316,6 +316,26 @@ __device__ __forceinline__ void block_sum4(double (&v)[4]) {
   for (int i = 0; i < 4; ++i) v[i] = s_t[i];
 }
 
+// The stop flag as one decision for the whole workgroup.  In the update
+// kernels workgroup 0 records the step's verdict in the flag while the other
+// workgroups of the same launch may still be reading it, so a wave-by-wave
+// test could split a workgroup: the waves that stay would then sum the LDS
+// slots of the waves that left (block_sum4/8) and update their entries with
+// those garbage totals.  Each wave reads the flag early (its latency hides
+// under the operand loads that follow), and the workgroup exits if any of
+// its waves saw it set.  That is the verdict every workgroup reaches from
+// the same totals anyway: the flag is set either by an earlier launch or by
+// this launch's workgroup 0 from bit-identical sums.
+__device__ __forceinline__ bool workgroup_stopped(int32_t seen) {
+  __shared__ int32_t s_seen[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) s_seen[threadIdx.x >> 6] = seen;
+  __syncthreads();
+  int32_t any = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) any |= s_seen[w];
+  return any != 0;
+}
+
 // Publish this workgroup's NV partial sums; returns true in every thread of
 // the last workgroup to arrive, whose v[] (all threads) then holds the
 // fixed-order total over all workgroups.
@@ -458,7 +478,9 @@ __global__ void __launch_bounds__(kBlock) k_cocg_spmv_dot(PatternDev pt, const V
   using C = typename Cx<R>::T;
   // the stop flag is read here and tested together with the first row's
   // bounds, a scalar load the row has to wait for anyway, so launches queued
-  // past convergence end before loading a row and working ones wait no longer
+  // past convergence end before loading a row and working ones wait no longer.
+  // No workgroup of this launch writes the flag (only the update kernels
+  // do), so every wave reads the same value and a per-wave exit is safe.
   const int32_t stopped = sc->done;
   const int lane = threadIdx.x & 63;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -531,9 +553,9 @@ __global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t n, const typenam
     }
   };
   load(i0);
-  // the stop flag is tested after the loads above are issued (it is the
-  // same for the whole grid, so every thread takes the same exit)
-  if (__builtin_amdgcn_readfirstlane(stopped)) return;
+  // the stop flag is tested after the loads above are issued, as one
+  // decision per workgroup (workgroup 0 of this launch may set it below)
+  if (workgroup_stopped(__builtin_amdgcn_readfirstlane(stopped))) return;
   double t[4];
   reduce_partials4(pin, nin, t);
   const double2 pq = make_double2(t[0], t[1]);
@@ -608,7 +630,7 @@ __global__ void __launch_bounds__(kBlock) k_cocg_pupdate(int64_t n, const typena
     }
   };
   load(i0);
-  if (__builtin_amdgcn_readfirstlane(stopped)) return;
+  if (workgroup_stopped(__builtin_amdgcn_readfirstlane(stopped))) return;
   double t[4];
   reduce_partials4(pin, nin, t);
   const double2 rho_new = make_double2(t[0], t[1]);
@@ -825,7 +847,7 @@ __global__ void __launch_bounds__(kBlock) k_sr_update(int64_t n, const double2* 
     }
   };
   load(i0);
-  if (__builtin_amdgcn_readfirstlane(stopped)) return;
+  if (workgroup_stopped(__builtin_amdgcn_readfirstlane(stopped))) return;
   double t[8];
   reduce_step_partials(pin_a, nin_a, pin_b, nin_b, t);
   const double2 delta = make_double2(t[0], t[1]);

@@ -293,6 +293,35 @@ def make_opts(precision=FEMH_FP64, rtol=1e-6, max_iter=0, inner_rtol=0.0, max_ou
     return o
 
 
+def check_device_tensor(t, dtype, min_numel: int, device: int, what: str):
+    """Refuse a tensor the C ABI cannot take safely: the entry points receive
+    bare device pointers and no lengths, so a host tensor, a wrong element
+    type, a strided view or a short buffer would turn into out-of-bounds
+    device accesses.  Raises FemhError(FEMH_E_INVALID)."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise FemhError(FEMH_E_INVALID, f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.device.type != "cuda" or (t.device.index if t.device.index is not None else 0) != device:
+        raise FemhError(FEMH_E_INVALID, f"{what}: tensor on {t.device}, the context is on cuda:{device}")
+    if t.dtype != dtype:
+        raise FemhError(FEMH_E_INVALID, f"{what}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise FemhError(FEMH_E_INVALID, f"{what}: tensor is not contiguous")
+    if t.numel() < min_numel:
+        raise FemhError(FEMH_E_INVALID, f"{what}: {t.numel()} elements, at least {min_numel} needed")
+
+
+def _vector_dtype(precision):
+    import torch
+
+    if precision == FEMH_MIXED:
+        return torch.complex64
+    if precision in (FEMH_FP64, FEMH_MIXED_MATRIX):
+        return torch.complex128
+    raise FemhError(FEMH_E_INVALID, f"unknown precision {precision}")
+
+
 # ----------------------------------------------------------- torch bridge
 class TorchAllocator:
     """femh_allocator backed by torch's caching allocator on one device and
@@ -418,6 +447,10 @@ class Problem:
 
     def solve_dev(self, waves, out_tensor, batched: bool = False, **opt_kw):
         """Device-output solve into a complex128 torch tensor of grid shape."""
+        import torch
+
+        check_device_tensor(out_tensor, torch.complex128, len(waves) * 3 * self.grid_nodes, self.ctx.device,
+                            "solve_dev output")
         w = make_waves(waves)
         o = make_opts(**opt_kw)
         stats = (femh_solve_stats * len(waves))()
@@ -450,11 +483,18 @@ class Problem:
         return d
 
     def spmv_dev(self, x, y, precision=FEMH_FP64, reps=1):
+        dt = _vector_dtype(precision)
+        check_device_tensor(x, dt, self.n_unknowns, self.ctx.device, "spmv_dev x")
+        check_device_tensor(y, dt, self.n_unknowns, self.ctx.device, "spmv_dev y")
         t = C.c_double()
         check(self.lib.femh_spmv_dev(self.handle, precision, x.data_ptr(), y.data_ptr(), reps, C.byref(t)))
         return t.value
 
     def spmv_half_dev(self, x, y, reps=1):
+        import torch
+
+        check_device_tensor(x, torch.complex128, self.n_unknowns, self.ctx.device, "spmv_half_dev x")
+        check_device_tensor(y, torch.complex128, self.n_unknowns, self.ctx.device, "spmv_half_dev y")
         t = C.c_double()
         check(self.lib.femh_spmv_half_dev(self.handle, x.data_ptr(), y.data_ptr(), reps, C.byref(t)))
         return t.value
@@ -468,6 +508,13 @@ class Problem:
         check(self.lib.femh_spmm_set_tile(self.handle, kind, blocks))
 
     def spmm_dev(self, X, Y, reps=1, precision=FEMH_MIXED_MATRIX):
+        import torch
+
+        if X.dim() != 2 or Y.shape != X.shape or X.shape[0] != self.n_unknowns or not 1 <= X.shape[1] <= 64:
+            raise FemhError(FEMH_E_INVALID, f"spmm_dev: X and Y must both be [{self.n_unknowns}, ncols] with "
+                                            f"1 <= ncols <= 64 (got {tuple(X.shape)} and {tuple(Y.shape)})")
+        check_device_tensor(X, torch.complex128, X.numel(), self.ctx.device, "spmm_dev X")
+        check_device_tensor(Y, torch.complex128, X.numel(), self.ctx.device, "spmm_dev Y")
         t = C.c_double()
         check(self.lib.femh_spmm_dev(self.handle, precision, X.shape[1], X.data_ptr(), Y.data_ptr(), reps,
                                      C.byref(t)))

@@ -239,3 +239,54 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(n, "size")] == C.sizeof(cls), n
         for fname, _ in cls._fields_:
             assert got[(n, fname)] == getattr(cls, fname).offset, (n, fname)
+
+
+def _bare_problem(n_unknowns=12, grid_nodes=8):
+    """A Problem wrapper with no device object behind it: the tensor checks
+    must refuse bad buffers before anything reaches the library."""
+    from types import SimpleNamespace
+
+    P = F.Problem.__new__(F.Problem)
+    P.handle = None
+    P.lib = None
+    P.ctx = SimpleNamespace(device=0)
+    P.n_unknowns = n_unknowns
+    P.grid_nodes = grid_nodes
+    P.n_nodes = n_unknowns // 3
+    P.spec = SimpleNamespace(nx=1, ny=1, nz=1)
+    return P
+
+
+def test_device_buffer_checks_refuse_host_tensors():
+    import torch
+
+    P = _bare_problem()
+    x = torch.zeros(12, dtype=torch.complex128)
+    for call in (lambda: P.spmv_dev(x, x), lambda: P.spmv_half_dev(x, x),
+                 lambda: P.spmm_dev(x.reshape(12, 1), x.reshape(12, 1)),
+                 lambda: P.solve_dev([], torch.zeros(0, dtype=torch.complex128))):
+        with pytest.raises(F.FemhError) as e:
+            call()
+        assert e.value.status == F.FEMH_E_INVALID
+
+
+def test_device_buffer_checks_refuse_bad_shapes_and_types():
+    import torch
+
+    P = _bare_problem()
+    # wrong element type for the precision: complex64 vectors are FEMH_MIXED only
+    with pytest.raises(F.FemhError, match="cuda"):
+        P.spmv_dev(torch.zeros(12, dtype=torch.complex64), torch.zeros(12, dtype=torch.complex64))
+    with pytest.raises(F.FemhError, match="unknown precision"):
+        P.spmv_dev(torch.zeros(12, dtype=torch.complex128), torch.zeros(12, dtype=torch.complex128), precision=7)
+    # SpMM blocks must be [n_unknowns, ncols], 1 <= ncols <= 64
+    for shape in ((11, 2), (12, 65), (12,)):
+        X = torch.zeros(shape, dtype=torch.complex128)
+        with pytest.raises(F.FemhError, match="spmm_dev"):
+            P.spmm_dev(X, X)
+    # the checker itself, on each property in turn
+    t = torch.zeros(12, dtype=torch.complex128)
+    with pytest.raises(F.FemhError, match="cuda"):
+        F.check_device_tensor(t, torch.complex128, 12, 0, "t")
+    with pytest.raises(F.FemhError, match="torch tensor"):
+        F.check_device_tensor(np.zeros(12, np.complex128), torch.complex128, 12, 0, "t")
