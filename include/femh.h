@@ -194,6 +194,25 @@ int femh_problem_create(femh_ctx* ctx, const femh_problem_desc* desc, femh_probl
 int femh_problem_get_info(const femh_problem* prob, femh_problem_info* info);
 void femh_problem_destroy(femh_problem* prob);
 
+/* A problem made from an already assembled matrix instead of a mesh: the
+ * global system of section 3 in 3x3 block CSR form, so that the solver of
+ * section 3.1.5 (Jacobi-preconditioned conjugate gradients read as COCG)
+ * and its products can run on a matrix built elsewhere (an oracle, another
+ * assembler).  nb block rows; row_ptr[nb + 1] with row_ptr[0] = 0 and
+ * row_ptr[nb] = nnzb; col_idx[nnzb] strictly ascending within each row,
+ * every row holding its diagonal block and at most 27 blocks (the
+ * neighbourhood of a hexahedral-mesh node); vals[nnzb][3][3] complex128,
+ * row-major blocks.  Host pointers, copied before the call returns.  The
+ * complex64 values are the round-to-nearest copy, the Jacobi inverse is
+ * 1 / the diagonal entries.  The problem has no mesh: femh_solve,
+ * femh_solve_dev, femh_solve_batched_dev and femh_export_rhs return
+ * FEMH_E_INVALID for it; femh_solve_rhs_dev, the products and the other
+ * export hooks work (grid_nodes reads 0).  Errors: FEMH_E_INVALID for a
+ * malformed pattern or a zero diagonal entry, FEMH_E_NONFINITE for a
+ * NaN/Inf value, FEMH_E_OOM. */
+int femh_import_bsr(femh_ctx* ctx, int64_t nb, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
+                    const femh_c128* vals, femh_problem** out);
+
 /* Solve for nrhs incident waves.  H_out (host) receives
  * [nrhs][nz+1][ny+1][nx+1][3] complex128 total-field values at the grid
  * nodes (0 at nodes of PEC elements only); stats (host) receives nrhs
@@ -205,6 +224,16 @@ int femh_solve(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves,
 /* As femh_solve, with H_out a device pointer of the same layout. */
 int femh_solve_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves,
                    const femh_solve_opts* opts, femh_c128* H_out_dev, femh_solve_stats* stats);
+
+/* Solve A x = b for nrhs given right-hand sides (section 3.1.5's solver
+ * on the assembled system, without the right-hand side of eq. (4) or the
+ * grid scatter): b_dev and x_dev are device arrays [nrhs][n_unknowns]
+ * complex128 in compact unknown order (3 * node + component); x_dev is
+ * overwritten (the iteration starts from x = 0).  Each column runs the
+ * single-right-hand-side solver of opts->precision, exactly as femh_solve
+ * does for the assembled right-hand side.  Statuses as femh_solve. */
+int femh_solve_rhs_dev(femh_problem* prob, int32_t nrhs, const femh_c128* b_dev, const femh_solve_opts* opts,
+                       femh_c128* x_dev, femh_solve_stats* stats);
 
 /* Batched right-hand sides: the nrhs (<= 64) columns advance together,
  * one block-sparse matrix times dense block (SpMM) per iteration, each
@@ -250,6 +279,14 @@ int femh_export_jacobi(const femh_problem* prob, femh_c128* dinv);
  * kernel time measured with HIP events on the context's stream. */
 int femh_spmv_dev(femh_problem* prob, int32_t precision, const void* x_dev, void* y_dev,
                   int32_t reps, double* avg_seconds);
+
+/* As femh_spmv_dev with host vectors x, y [n_unknowns] complex128: for
+ * FEMH_MIXED x is rounded to complex64 on the host, the complex64 product
+ * runs on the device and y is widened back; the other precisions take the
+ * complex128 vectors as they are.  The timing covers the device products
+ * only, not the copies. */
+int femh_spmv(femh_problem* prob, int32_t precision, const femh_c128* x, femh_c128* y, int32_t reps,
+              double* avg_seconds);
 
 /* Y = A X for ncols (1..64) columns: X and Y complex128 device arrays
  * [n_unknowns][ncols] (column index fastest), the batched solver's wide

@@ -57,6 +57,7 @@ constexpr int kSlabY = 8;
 
 int ensure_row_order(Problem* P) {
   if (P->row_order) return FEMH_OK;
+  if (P->imported) return FEMH_OK;  // no mesh: the rows keep their own order
   const int32_t nn = P->pat.nn;
   const int gx = P->mesh.nx + 1, gy = P->mesh.ny + 1, gz = P->mesh.nz + 1;
   std::vector<int32_t> grid((size_t)nn), order((size_t)nn);

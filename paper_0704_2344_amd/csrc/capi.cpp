@@ -40,6 +40,26 @@ struct DevTmp {
 
 }  // namespace
 
+static int require_mesh(const femh_problem* prob) {
+  if (prob->imported) {
+    femh::set_error("the problem was imported as a matrix and has no mesh: solve with femh_solve_rhs_dev");
+    return FEMH_E_INVALID;
+  }
+  return FEMH_OK;
+}
+
+static int check_opts(const femh_solve_opts& o) {
+  if (o.precision != FEMH_FP64 && o.precision != FEMH_MIXED && o.precision != FEMH_MIXED_MATRIX) {
+    femh::set_error("unknown precision %d", o.precision);
+    return FEMH_E_INVALID;
+  }
+  if (o.precond != FEMH_PRECOND_JACOBI && o.precond != FEMH_PRECOND_NONE) {
+    femh::set_error("unknown preconditioner %d", o.precond);
+    return FEMH_E_INVALID;
+  }
+  return FEMH_OK;
+}
+
 extern "C" {
 
 const char* femh_last_error(void) { return femh::last_error(); }
@@ -172,6 +192,44 @@ void femh_problem_destroy(femh_problem* p) {
   delete static_cast<Problem*>(p);
 }
 
+int femh_import_bsr(femh_ctx* ctx, int64_t nb, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
+                    const femh_c128* vals, femh_problem** out) {
+  femh::clear_error();
+  if (!ctx || !out) {
+    femh::set_error("ctx and out must not be NULL");
+    return FEMH_E_INVALID;
+  }
+  *out = nullptr;
+  FEMH_TRY_HIP(hipSetDevice(ctx->device));
+  Problem* P = nullptr;
+  int st = femh::problem_import(ctx, nb, nnzb, row_ptr, col_idx, vals, &P);
+  if (st != FEMH_OK) return st;
+  *out = static_cast<femh_problem*>(P);
+  return FEMH_OK;
+}
+
+int femh_solve_rhs_dev(femh_problem* prob, int32_t nrhs, const femh_c128* b_dev, const femh_solve_opts* opts,
+                       femh_c128* x_dev, femh_solve_stats* stats) {
+  femh::clear_error();
+  if (!prob || !b_dev || !x_dev || !stats || nrhs < 1) {
+    femh::set_error("prob, b, x and stats must not be NULL; nrhs >= 1");
+    return FEMH_E_INVALID;
+  }
+  const femh_solve_opts o = femh::opts_with_defaults(opts);
+  FEMH_TRY(check_opts(o));
+  Ctx* c = prob->ctx;
+  FEMH_TRY_HIP(hipSetDevice(c->device));
+  const int64_t n = 3 * (int64_t)prob->pat.nn;
+  int first_bad = FEMH_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    int rc = femh::solve_single(prob, (const double2*)b_dev + r * n, (double2*)x_dev + r * n, o, &stats[r]);
+    if (rc != FEMH_OK && rc != FEMH_E_NOT_CONVERGED && rc != FEMH_E_BREAKDOWN) return rc;
+    if (rc != FEMH_OK && first_bad == FEMH_OK) first_bad = rc;
+  }
+  FEMH_TRY_HIP(hipStreamSynchronize(c->stream));
+  return first_bad;
+}
+
 static int upload_waves(Ctx* c, int32_t nrhs, const femh_plane_wave* waves, DevTmp& dw) {
   if (!dw.p) {
     femh::set_error("device allocation failed (waves)");
@@ -188,6 +246,7 @@ int femh_solve_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* wave
     femh::set_error("prob, H_out and stats must not be NULL");
     return FEMH_E_INVALID;
   }
+  FEMH_TRY(require_mesh(prob));
   std::string m;
   int st = femh::validate_waves(nrhs, waves, m);
   if (st != FEMH_OK) {
@@ -195,14 +254,7 @@ int femh_solve_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wave* wave
     return st;
   }
   const femh_solve_opts o = femh::opts_with_defaults(opts);
-  if (o.precision != FEMH_FP64 && o.precision != FEMH_MIXED && o.precision != FEMH_MIXED_MATRIX) {
-    femh::set_error("unknown precision %d", o.precision);
-    return FEMH_E_INVALID;
-  }
-  if (o.precond != FEMH_PRECOND_JACOBI && o.precond != FEMH_PRECOND_NONE) {
-    femh::set_error("unknown preconditioner %d", o.precond);
-    return FEMH_E_INVALID;
-  }
+  FEMH_TRY(check_opts(o));
   Ctx* c = prob->ctx;
   FEMH_TRY_HIP(hipSetDevice(c->device));
   const int64_t n = 3 * (int64_t)prob->pat.nn;
@@ -234,6 +286,7 @@ int femh_solve(femh_problem* prob, int32_t nrhs, const femh_plane_wave* waves, c
     femh::set_error("prob, H_out and stats must not be NULL; nrhs >= 1");
     return FEMH_E_INVALID;
   }
+  FEMH_TRY(require_mesh(prob));
   Ctx* c = prob->ctx;
   const size_t bytes = sizeof(femh_c128) * 3 * (size_t)prob->grid_nodes * nrhs;
   DevTmp dh(c, bytes);
@@ -259,6 +312,7 @@ int femh_solve_batched_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wa
     femh::set_error("batched solve takes 1..64 right-hand sides (got %d)", nrhs);
     return FEMH_E_INVALID;
   }
+  FEMH_TRY(require_mesh(prob));
   std::string m;
   int st = femh::validate_waves(nrhs, waves, m);
   if (st != FEMH_OK) {
@@ -404,6 +458,7 @@ int femh_export_rhs(femh_problem* p, int32_t nrhs, const femh_plane_wave* waves,
     femh::set_error("NULL argument");
     return FEMH_E_INVALID;
   }
+  FEMH_TRY(require_mesh(p));
   std::string m;
   int st = femh::validate_waves(nrhs, waves, m);
   if (st != FEMH_OK) {
@@ -463,6 +518,46 @@ int femh_spmv_dev(femh_problem* p, int32_t precision, const void* x, void* y, in
   if (avg_seconds) *avg_seconds = ms * 1e-3 / reps;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  return FEMH_OK;
+}
+
+int femh_spmv(femh_problem* p, int32_t precision, const femh_c128* x, femh_c128* y, int32_t reps,
+              double* avg_seconds) {
+  femh::clear_error();
+  if (!p || !x || !y || reps < 1 ||
+      (precision != FEMH_FP64 && precision != FEMH_MIXED && precision != FEMH_MIXED_MATRIX)) {
+    femh::set_error("bad spmv arguments");
+    return FEMH_E_INVALID;
+  }
+  Ctx* c = p->ctx;
+  FEMH_TRY_HIP(hipSetDevice(c->device));
+  const int64_t n = 3 * (int64_t)p->pat.nn;
+  const bool c64 = precision == FEMH_MIXED;
+  const size_t vb = c64 ? 8 : 16;
+  DevTmp dx(c, vb * n), dy(c, vb * n);
+  if (!dx.p || !dy.p) {
+    femh::set_error("device allocation failed (spmv vectors)");
+    return FEMH_E_OOM;
+  }
+  std::vector<float2> h32;
+  if (c64) {
+    // complex64 vectors: the input rounded to nearest on the host
+    h32.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) h32[i] = make_float2((float)x[i].re, (float)x[i].im);
+    FEMH_TRY_HIP(hipMemcpyAsync(dx.p, h32.data(), vb * n, hipMemcpyHostToDevice, c->stream));
+  } else {
+    FEMH_TRY_HIP(hipMemcpyAsync(dx.p, x, vb * n, hipMemcpyHostToDevice, c->stream));
+  }
+  int rc = femh_spmv_dev(p, precision, dx.p, dy.p, reps, avg_seconds);
+  if (rc != FEMH_OK) return rc;
+  if (c64) {
+    FEMH_TRY_HIP(hipMemcpyAsync(h32.data(), dy.p, vb * n, hipMemcpyDeviceToHost, c->stream));
+    FEMH_TRY_HIP(hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n; ++i) y[i] = femh_c128{(double)h32[i].x, (double)h32[i].y};
+  } else {
+    FEMH_TRY_HIP(hipMemcpyAsync(y, dy.p, vb * n, hipMemcpyDeviceToHost, c->stream));
+    FEMH_TRY_HIP(hipStreamSynchronize(c->stream));
+  }
   return FEMH_OK;
 }
 

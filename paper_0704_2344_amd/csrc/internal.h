@@ -174,6 +174,11 @@ hipError_t rhs(hipStream_t st, const MeshDev& m, const PatternDev& p, int32_t nr
 hipError_t scatter(hipStream_t st, const MeshDev& m, const PatternDev& p, int32_t nrhs,
                    const double2* x, double2* out);
 hipError_t copy_probe(hipStream_t st, const float4* src, float4* dst, int64_t n);
+// imported matrices: complex64 rounding of the values, and the Jacobi
+// inverse from the diagonal blocks (*bad = 1 on a zero diagonal entry)
+hipError_t round_c64(hipStream_t st, int64_t n, const double2* v64, float2* v32);
+hipError_t dinv_from_blocks(hipStream_t st, int32_t nn, const int32_t* row_ptr, const int32_t* col_idx,
+                            const double2* val64, double2* dinv64, float2* dinv32, int32_t* bad);
 
 // ---- Krylov kernels
 struct SpmvLaunch {
@@ -322,6 +327,7 @@ struct Problem {
   int32_t* hpos = nullptr;        // symmetric half store: per block slot index (device, [nnzb])
   double2* hval64 = nullptr;      // symmetric half store values (device, [stored][9])
   int64_t n_half = 0;             // stored blocks
+  bool imported = false;          // built by femh_import_bsr: pattern and values only, no mesh
 
   std::vector<void*> owned;
   void* alloc(size_t bytes);  // tracked allocation, freed with the problem
@@ -335,6 +341,11 @@ int64_t estimate_bytes(const femh_problem_desc* d, int32_t nrhs, int32_t precisi
 // Extra device bytes of solving nrhs waves as batched groups of up to four.
 int64_t estimate_batch_workspace(const femh_problem_desc* d, int32_t nrhs);
 int problem_create(Ctx* ctx, const femh_problem_desc* d, Problem** out);
+// A problem from a host block-CSR matrix (no mesh): validates the pattern,
+// copies it and the complex128 values, derives the complex64 values and
+// the Jacobi inverse.
+int problem_import(Ctx* ctx, int64_t nb, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
+                   const femh_c128* vals, Problem** out);
 femh_solve_opts opts_with_defaults(const femh_solve_opts* o);
 
 // Solve one right-hand side already assembled into b (device, FP64) into x

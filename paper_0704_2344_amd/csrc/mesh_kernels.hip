@@ -435,9 +435,60 @@ __global__ void k_copy_probe(const float4* __restrict__ src, float4* __restrict_
 
 inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// ------------------------------------------------------ imported matrices
+// complex64 copy of imported complex128 values (round to nearest, as the
+// assembly writes it)
+__global__ void k_round_c64(int64_t n, const double2* __restrict__ v64, float2* __restrict__ v32) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double2 v = v64[t];
+  v32[t] = make_float2((float)v.x, (float)v.y);
+}
+
+// Jacobi inverse from an imported matrix's diagonal blocks: row a's block
+// with column a (the host checked that it exists); bad gets 1 when a
+// diagonal entry is zero
+__global__ void k_dinv_from_blocks(int32_t nn, const int32_t* __restrict__ row_ptr,
+                                   const int32_t* __restrict__ col_idx, const double2* __restrict__ val64,
+                                   double2* __restrict__ dinv64, float2* __restrict__ dinv32,
+                                   int32_t* __restrict__ bad) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * (int64_t)nn) return;
+  const int32_t a = (int32_t)(t / 3);
+  const int i = (int)(t % 3);
+  int32_t k = row_ptr[a];
+  while (k < row_ptr[a + 1] - 1 && col_idx[k] != a) ++k;
+  const double2 d = val64[(int64_t)k * 9 + 4 * i];
+  if (d.x == 0.0 && d.y == 0.0) {
+    *bad = 1;
+    dinv64[t] = make_double2(0.0, 0.0);
+    dinv32[t] = make_float2(0.f, 0.f);
+    return;
+  }
+  const double2 inv = cinv(d);
+  dinv64[t] = inv;
+  dinv32[t] = make_float2((float)inv.x, (float)inv.y);
+}
+
 }  // namespace
 
 namespace k {
+
+hipError_t round_c64(hipStream_t st, int64_t n, const double2* v64, float2* v32) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_round_c64, dim3(grid_for(n, 256)), dim3(256), 0, st, n, v64, v32);
+  return hipGetLastError();
+}
+
+hipError_t dinv_from_blocks(hipStream_t st, int32_t nn, const int32_t* row_ptr, const int32_t* col_idx,
+                            const double2* val64, double2* dinv64, float2* dinv32, int32_t* bad) {
+  const int64_t n = 3 * (int64_t)nn;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dinv_from_blocks, dim3(grid_for(n, 256)), dim3(256), 0, st, nn, row_ptr, col_idx, val64,
+                     dinv64, dinv32, bad);
+  return hipGetLastError();
+}
+
 
 int64_t scan_tmp_ints(int64_t n) {
   int64_t total = 0;

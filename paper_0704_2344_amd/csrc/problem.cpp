@@ -452,6 +452,94 @@ int problem_create(Ctx* ctx, const femh_problem_desc* d, Problem** out) {
   return FEMH_OK;
 }
 
+int problem_import(Ctx* ctx, int64_t nb, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
+                   const femh_c128* vals, Problem** out) {
+  if (!row_ptr || !col_idx || !vals || !out) {
+    set_error("row_ptr, col_idx, vals and out must not be NULL");
+    return FEMH_E_INVALID;
+  }
+  if (nb < 1 || nb > (int64_t)1 << 30 || nnzb < nb || nnzb > ((int64_t)1 << 31) - 1) {
+    set_error("need 1 <= nb <= 2^30 block rows and nb <= nnzb < 2^31 blocks (got %lld, %lld)", (long long)nb,
+              (long long)nnzb);
+    return FEMH_E_INVALID;
+  }
+  if (row_ptr[0] != 0 || row_ptr[nb] != nnzb) {
+    set_error("row_ptr must start at 0 and end at nnzb");
+    return FEMH_E_INVALID;
+  }
+  for (int64_t a = 0; a < nb; ++a) {
+    const int32_t b0 = row_ptr[a], b1 = row_ptr[a + 1];
+    // the products' lane mappings cover the 27 neighbours of a hexahedral
+    // mesh node
+    if (b1 <= b0 || b1 - b0 > 27) {
+      set_error("block row %lld holds %d blocks (1..27 allowed)", (long long)a, b1 - b0);
+      return FEMH_E_INVALID;
+    }
+    bool diag = false;
+    for (int32_t k = b0; k < b1; ++k) {
+      if (col_idx[k] < 0 || col_idx[k] >= nb || (k > b0 && col_idx[k] <= col_idx[k - 1])) {
+        set_error("block row %lld: column indices must ascend strictly within [0, nb)", (long long)a);
+        return FEMH_E_INVALID;
+      }
+      diag |= col_idx[k] == a;
+    }
+    if (!diag) {
+      set_error("block row %lld has no diagonal block", (long long)a);
+      return FEMH_E_INVALID;
+    }
+  }
+  for (int64_t q = 0; q < 9 * nnzb; ++q)
+    if (!std::isfinite(vals[q].re) || !std::isfinite(vals[q].im)) {
+      set_error("vals has a non-finite entry");
+      return FEMH_E_NONFINITE;
+    }
+  Problem* P = new Problem();
+  P->ctx = ctx;
+  P->imported = true;
+  hipStream_t s = ctx->stream;
+  const int32_t nn = (int32_t)nb;
+  P->row_ptr = (int32_t*)P->alloc(4 * (size_t)(nn + 1));
+  P->col_idx = (int32_t*)P->alloc(4 * (size_t)nnzb);
+  P->val64 = (double2*)P->alloc(144 * (size_t)nnzb + 16);
+  P->val32 = (float2*)P->alloc(72 * (size_t)nnzb + 16);
+  P->dinv64 = (double2*)P->alloc(48 * (size_t)nn);
+  P->dinv32 = (float2*)P->alloc(24 * (size_t)nn);
+  TmpBuf bad(ctx, 64);
+  if (!P->row_ptr || !P->col_idx || !P->val64 || !P->val32 || !P->dinv64 || !P->dinv32 || !bad.p) {
+    set_error("device allocation failed (imported matrix)");
+    delete P;
+    return FEMH_E_OOM;
+  }
+  int32_t* hostw = reinterpret_cast<int32_t*>(ctx->pinned);
+  hipError_t e = hipMemcpyAsync(P->row_ptr, row_ptr, 4 * (size_t)(nn + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->col_idx, col_idx, 4 * (size_t)nnzb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->val64, vals, 144 * (size_t)nnzb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(bad.p, 0, 4, s);
+  if (e == hipSuccess) e = k::round_c64(s, 9 * nnzb, P->val64, P->val32);
+  if (e == hipSuccess)
+    e = k::dinv_from_blocks(s, nn, P->row_ptr, P->col_idx, P->val64, P->dinv64, P->dinv32, bad.as<int32_t>());
+  if (e == hipSuccess) e = hipMemcpyAsync(hostw, bad.p, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    set_error("importing the matrix failed: %s", hipGetErrorString(e));
+    delete P;
+    return FEMH_E_DEVICE;
+  }
+  if (hostw[0]) {
+    set_error("a diagonal entry of the matrix is zero (no Jacobi inverse)");
+    delete P;
+    return FEMH_E_INVALID;
+  }
+  P->pat.nn = nn;
+  P->pat.nnzb = nnzb;
+  P->pat.row_ptr = P->row_ptr;
+  P->pat.col_idx = P->col_idx;
+  P->grid_nodes = 0;
+  P->spmv = k::spmv_launch_for(nn, ctx->n_cu);
+  *out = P;
+  return FEMH_OK;
+}
+
 femh_solve_opts opts_with_defaults(const femh_solve_opts* o) {
   femh_solve_opts r{};
   if (o) r = *o;

@@ -128,6 +128,9 @@ SIGNATURES = {
     "femh_problem_create": (C.c_int, [P, C.POINTER(femh_problem_desc), C.POINTER(P)]),
     "femh_problem_get_info": (C.c_int, [P, C.POINTER(femh_problem_info)]),
     "femh_problem_destroy": (None, [P]),
+    "femh_import_bsr": (C.c_int, [P, I64, I64, P, P, P, C.POINTER(P)]),
+    "femh_solve_rhs_dev": (C.c_int, [P, I32, P, C.POINTER(femh_solve_opts), P, C.POINTER(femh_solve_stats)]),
+    "femh_spmv": (C.c_int, [P, I32, P, P, I32, PD]),
     "femh_solve": (C.c_int, [P, I32, C.POINTER(femh_plane_wave), C.POINTER(femh_solve_opts), P,
                              C.POINTER(femh_solve_stats)]),
     "femh_solve_dev": (C.c_int, [P, I32, C.POINTER(femh_plane_wave), C.POINTER(femh_solve_opts), P,
@@ -419,6 +422,60 @@ class Problem:
         self.n_unknowns = info.n_unknowns
         self.nnzb = info.nnzb
         self.grid_nodes = info.grid_nodes
+
+    @classmethod
+    def from_bsr(cls, ctx: Context, row_ptr, col_idx, vals):
+        """A problem made from an assembled block matrix (femh_import_bsr):
+        row_ptr [nb + 1], col_idx [nnzb], vals [nnzb, 3, 3] complex128, host
+        arrays.  It has no mesh: solve it with solve_rhs_dev."""
+        rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int32))
+        ci = np.ascontiguousarray(np.asarray(col_idx, dtype=np.int32))
+        v = np.ascontiguousarray(np.asarray(vals, dtype=np.complex128))
+        if v.shape != (len(ci), 3, 3) or len(rp) < 2:
+            raise FemhError(FEMH_E_INVALID, f"vals must be [nnzb, 3, 3] with nnzb = len(col_idx) (got {v.shape})")
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.spec = None
+        h = C.c_void_p()
+        check(self.lib.femh_import_bsr(ctx.handle, len(rp) - 1, len(ci), rp.ctypes.data, ci.ctypes.data,
+                                       v.ctypes.data, C.byref(h)))
+        self.handle = h
+        ctx.children.add(self)
+        _live_children.add(self)
+        info = femh_problem_info()
+        check(self.lib.femh_problem_get_info(h, C.byref(info)))
+        self.info = info
+        self.n_nodes = info.n_nodes
+        self.n_unknowns = info.n_unknowns
+        self.nnzb = info.nnzb
+        self.grid_nodes = info.grid_nodes
+        return self
+
+    def solve_rhs_dev(self, b, x, **opt_kw):
+        """Solve A x = b for given right-hand sides: b and x complex128 device
+        tensors [nrhs, n_unknowns] (or [n_unknowns]); x is overwritten."""
+        import torch
+
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        n = nrhs * self.n_unknowns
+        check_device_tensor(b, torch.complex128, n, self.ctx.device, "solve_rhs_dev b")
+        check_device_tensor(x, torch.complex128, n, self.ctx.device, "solve_rhs_dev x")
+        o = make_opts(**opt_kw)
+        stats = (femh_solve_stats * nrhs)()
+        st = self.lib.femh_solve_rhs_dev(self.handle, nrhs, b.data_ptr(), C.byref(o), x.data_ptr(), stats)
+        check(st, ok=(FEMH_OK, FEMH_E_NOT_CONVERGED, FEMH_E_BREAKDOWN))
+        return [s.as_dict() for s in stats], st
+
+    def spmv(self, x, precision=FEMH_FP64, reps=1):
+        """Host-vector product (femh_spmv): returns (y, mean device seconds)."""
+        xv = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+        if xv.shape != (self.n_unknowns,):
+            raise FemhError(FEMH_E_INVALID, f"x must have {self.n_unknowns} entries")
+        y = np.zeros_like(xv)
+        t = C.c_double()
+        check(self.lib.femh_spmv(self.handle, precision, xv.ctypes.data, y.ctypes.data, reps, C.byref(t)))
+        return y, t.value
 
     def close(self):
         if self.handle:
