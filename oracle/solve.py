@@ -90,12 +90,21 @@ def residual(A, x, b):
     return float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
 
 
-def condest(A):
+def condest(A, lu=None):
     """1-norm condition estimate ||A||_1 * est(||A^-1||_1): SuperLU solves
-    inside the Hager-Higham estimator (scipy onenormest)."""
-    lu = spla.splu(sp.csc_matrix(A))
+    inside the Hager-Higham estimator (scipy onenormest).  lu may be a
+    SuperLU factorisation of A already at hand (see lu_solve_condest)."""
+    if lu is None:
+        lu = spla.splu(sp.csc_matrix(A))
     n = A.shape[0]
     inv = spla.LinearOperator((n, n), matvec=lu.solve,
                               rmatvec=lambda y: lu.solve(np.asarray(y, np.complex128), trans="H"),
                               dtype=np.complex128)
     return float(spla.norm(A, 1) * spla.onenormest(inv))
+
+
+def lu_solve_condest(A, b):
+    """SuperLU solution of A x = b and the 1-norm condition estimate from the
+    same factorisation (one factorisation instead of two for large systems)."""
+    lu = spla.splu(sp.csc_matrix(A))
+    return lu.solve(np.asarray(b, dtype=np.complex128)), condest(A, lu)

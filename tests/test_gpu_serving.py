@@ -185,3 +185,40 @@ def test_batch_rhs_cancel_and_admission(ctx):
     rep = srv.report()
     assert rep["peak_resident_bytes"] <= 96 << 20 and rep["completed"] == 3
     srv.close()
+
+
+@pytest.mark.parametrize("batch", [False, True])
+@pytest.mark.parametrize("prec", [F.FEMH_FP64, F.FEMH_MIXED_MATRIX, F.FEMH_MIXED])
+def test_served_fields_match_the_oracle(ctx, prec, batch):
+    """Requests of different sizes served together (they overlap on the
+    device) against the CPU oracle: the oracle's scalar assembly, SuperLU
+    solution and 1-norm condition estimate, the solve tolerance chosen as
+    0.1 * target / kappa so that the forward error is certified below the
+    target (1e-9 FP64, 1e-6 mixed).  Each field must match the oracle's at
+    every active node to the target and be exactly zero at the nodes of PEC
+    elements only."""
+    from oracle import fem, solve
+
+    if batch and prec == F.FEMH_MIXED:
+        pytest.skip("the batched server groups run FP64 directions (FEMH_MIXED maps to the complex64 matrix)")
+    target = 1e-9 if prec == F.FEMH_FP64 else 1e-6
+    reqs = _requests(31, 4, n_hi=12)
+    refs = []
+    for p, w in reqs:
+        A = fem.assemble(p)
+        X = solve.sparse_solve(A, fem.rhs(p, w))
+        kappa = solve.condest(A)
+        refs.append((fem.scatter_to_grid(p, X), min(1e-7, 0.1 * target / kappa), fem.Mesh(p).node_active))
+    srv = F.Server(ctx, max_slots=8, chunk_iters=16, batch_rhs=batch)
+    tickets = [srv.submit(p, w, precision=prec, rtol=rtol) for (p, w), (_, rtol, _) in zip(reqs, refs)]
+    for (p, w), t, (Ho, rtol, active) in zip(reqs, tickets, refs):
+        st, H, stats = srv.poll(t, len(w), _shape(p, len(w)))
+        assert st == F.FEMH_OK, stats
+        for r in range(len(w)):
+            err = np.linalg.norm(H[r] - Ho[r]) / np.linalg.norm(Ho[r])
+            assert err <= target, (prec, batch, r, err, rtol, stats[r])
+            assert stats[r]["rel_residual"] <= rtol
+        assert np.all(H[:, ~active] == 0)
+    rep = srv.report()
+    assert rep["failed"] == 0 and rep["completed"] == len(reqs)
+    srv.close()

@@ -529,3 +529,42 @@ def test_printed_penalty_term_with_symmetrisation_breaks_the_empty_box():
     e_sym = err(((A + S) + (A + S).T) / 2)
     assert e_a3 < 0.06 and e_lit < 0.1
     assert e_sym > 0.5
+
+
+def test_condition_estimate_brackets_the_exact_condition_number():
+    """The Hager-Higham estimate is a lower bound of ||A||_1 ||A^-1||_1 and,
+    on these small systems, within a factor 10 of it, also from the
+    shared-factorisation variant, whose solution is the dense one."""
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        p = W.random_small(rng, n=(3, 3, 2), n_pec=1, lossy=True)
+        A = fem.assemble(p)
+        exact = float(abs(np.linalg.cond(A.toarray(), 1)))
+        est = solve.condest(A)
+        assert exact / 10.0 <= est <= exact * (1 + 1e-10), (est, exact)
+        b = fem.rhs(p, [W.random_wave(rng)])[:, 0]
+        x, est2 = solve.lu_solve_condest(A, b)   # the estimator draws its own start vectors
+        assert exact / 10.0 <= est2 <= exact * (1 + 1e-10), (est2, exact)
+        xd = solve.dense_solve(A, b)
+        assert np.linalg.norm(x - xd) <= 1e-12 * np.linalg.norm(xd)
+
+
+def test_bsr_blocks_and_grid_scatter_are_lossless():
+    """to_bsr_blocks cuts the scalar matrix into the 3x3 blocks of the block
+    pattern with nothing left over (the blocks reassemble A exactly), and
+    scatter_to_grid puts every unknown at its node and zeros elsewhere."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(13)
+    p = W.random_small(rng, n=(4, 3, 3), n_pec=3)
+    A = fem.assemble(p)
+    rp, ci = fem.block_pattern(p)
+    blocks = fem.to_bsr_blocks(A, rp, ci)
+    B = sp.bsr_matrix((blocks, ci, rp), shape=A.shape).tocsr()
+    assert abs(B - A).max() == 0.0
+    mesh = fem.Mesh(p)
+    x = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    H = fem.scatter_to_grid(p, x)
+    assert H.shape == (1, p.nz + 1, p.ny + 1, p.nx + 1, 3)
+    np.testing.assert_array_equal(H[0][mesh.node_active].reshape(-1), x)
+    assert np.all(H[0][~mesh.node_active] == 0)
