@@ -1,16 +1,21 @@
 // Continuous-batching request loop.
 //
-// A server thread owns a few internal contexts, one HIP stream each
-// (default priority; device memory from hipMalloc).  Submitted requests wait
-// in a FIFO queue; the loop admits them (first fit within a small window) as
-// long as a slot is free and their estimated device footprint fits the
-// budget, assembles each admitted problem on the next stream, and creates
-// one solver state machine per right-hand side.  Every round it advances all
-// resident right-hand sides of all requests (each queues its next chunk of
-// iterations without waiting), so requests of different sizes overlap on
-// the device; a request whose columns have all finished (or that was
-// cancelled) is retired at once: its field is scattered, copied to host
-// memory and its device memory released for the next admission.
+// A stepping thread and a set-up thread share a few internal contexts, one
+// HIP stream each (default priority; device memory from hipMalloc).
+// Submitted requests wait in a FIFO queue; the stepping thread admits them
+// (first fit within a small window) as long as a slot is free and their
+// estimated device footprint fits the budget, and hands each admitted
+// request to the set-up thread, which assembles its problem on the next
+// stream and creates one solver state machine per right-hand side (or per
+// group of up to four).  Every round the stepping thread advances all
+// resident, set-up right-hand sides of all requests (each queues its next
+// chunk of iterations without waiting), so requests of different sizes
+// overlap on the device; a request whose columns have all finished (or that
+// was cancelled) goes back to the set-up thread, which scatters its field,
+// copies it to host memory and releases its device memory for the next
+// admission.  Assembly, the host synchronisations it needs and the
+// retirement copies therefore never hold up the iterations of the requests
+// already resident.
 //
 // Each right-hand side runs exactly the single-solve code path with its own
 // buffers and deterministic kernels, so a request's result does not depend
@@ -44,6 +49,8 @@ struct Request {
   double t_submit = 0, t_start = 0, t_done = 0;
   enum State { QUEUED, RUNNING, FINISHED } state = QUEUED;
   bool cancel = false;
+  bool ready = false;    // set up: the stepping thread may advance it
+  bool handed = false;   // handed back for retirement: the stepping thread no longer touches it
   int status = FEMH_OK;
   std::vector<femh_solve_stats> stats;
   std::vector<femh_c128> H;
@@ -74,7 +81,16 @@ struct femh_server {
   std::map<uint64_t, Request*> all;
   uint64_t next_ticket = 1;
   bool stop = false;
-  std::thread th;
+  std::thread th, io;
+  // set-up thread work: requests to set up (status unused) or to retire
+  struct Job {
+    Request* r;
+    bool retire;
+    int status;
+  };
+  std::deque<Job> jobs;
+  std::condition_variable cv_io;
+  bool io_stop = false;
   int64_t resident = 0, peak = 0;
   // report
   int64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, rejected = 0, rhs_completed = 0;
@@ -83,6 +99,8 @@ struct femh_server {
   int next_lane = 0;
 
   void loop();
+  void io_loop();
+  void hand_back(Request* r, int status);
   void admit_locked(std::vector<Request*>& admitted);
   int setup(Request* r);
   void retire(Request* r, int status);
@@ -249,6 +267,39 @@ void femh_server::retire(Request* r, int status) {
   cv_done.notify_all();
 }
 
+void femh_server::hand_back(Request* r, int status) {
+  std::lock_guard<std::mutex> g(mu);
+  r->handed = true;
+  jobs.push_back(Job{r, true, status});
+  cv_io.notify_all();
+}
+
+void femh_server::io_loop() {
+  (void)hipSetDevice(base->device);
+  while (true) {
+    Job j;
+    {
+      std::unique_lock<std::mutex> g(mu);
+      cv_io.wait(g, [this] { return io_stop || !jobs.empty(); });
+      if (jobs.empty()) break;  // io_stop with nothing left
+      j = jobs.front();
+      jobs.pop_front();
+    }
+    if (j.retire) {
+      retire(j.r, j.status);
+      continue;
+    }
+    const int st = setup(j.r);
+    if (st != FEMH_OK) {
+      retire(j.r, st);
+      continue;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    j.r->ready = true;
+    cv_work.notify_all();
+  }
+}
+
 void femh_server::loop() {
   (void)hipSetDevice(base->device);
   std::vector<Request*> active;
@@ -258,33 +309,28 @@ void femh_server::loop() {
       std::unique_lock<std::mutex> g(mu);
       if (stop) break;
       admit_locked(admitted);
-      if (running.empty()) {
-        cv_work.wait_for(g, std::chrono::milliseconds(20));
+      for (Request* r : admitted) jobs.push_back(Job{r, false, FEMH_OK});
+      if (!admitted.empty()) cv_io.notify_all();
+      // the requests this thread may advance: set up and not handed back
+      active.clear();
+      for (Request* r : running)
+        if (r->ready && !r->handed) active.push_back(r);
+      if (active.empty()) {
+        cv_work.wait_for(g, std::chrono::milliseconds(running.empty() ? 20 : 1));
         continue;
       }
-    }
-    for (Request* r : admitted) {
-      int st = setup(r);
-      if (st != FEMH_OK) retire(r, st);
-    }
-    {
-      // only this thread retires requests, so everything in `active` stays
-      // alive for the round
-      std::lock_guard<std::mutex> g(mu);
-      active = running;
     }
     bool any_progress = false;
     femh::Stepper* waiter = nullptr;
     femh::BatchStepper* bwaiter = nullptr;
     for (Request* r : active) {
-      if (r->state != Request::RUNNING || (r->steps.empty() && r->bsteps.empty())) continue;
       bool cancel;
       {
         std::lock_guard<std::mutex> g(mu);
         cancel = r->cancel;
       }
       if (cancel) {
-        retire(r, FEMH_E_CANCELLED);
+        hand_back(r, FEMH_E_CANCELLED);
         any_progress = true;
         continue;
       }
@@ -320,22 +366,26 @@ void femh_server::loop() {
         }
       }
       if (err != FEMH_OK) {
-        retire(r, err);
+        hand_back(r, err);
+        any_progress = true;
       } else if (all_done) {
-        retire(r, FEMH_OK);
+        hand_back(r, FEMH_OK);
         any_progress = true;
       }
     }
     if (!any_progress && waiter) femh::stepper_wait(waiter);
     if (!any_progress && bwaiter) femh::batch_stepper_wait(bwaiter);
   }
-  // shut down: cancel whatever is left
-  std::vector<Request*> left;
-  {
-    std::lock_guard<std::mutex> g(mu);
-    left = running;
-  }
-  for (Request* r : left) retire(r, FEMH_E_CANCELLED);
+  // shut down: hand every request still resident back as cancelled (the
+  // set-up thread finishes its queue, then these)
+  std::lock_guard<std::mutex> g(mu);
+  for (Request* r : running)
+    if (!r->handed) {
+      r->handed = true;
+      jobs.push_back(Job{r, true, FEMH_E_CANCELLED});
+    }
+  io_stop = true;
+  cv_io.notify_all();
 }
 
 extern "C" {
@@ -393,6 +443,7 @@ int femh_server_create(femh_ctx* ctx_, const femh_server_opts* opts, femh_server
     s->lanes.push_back(c);
   }
   s->th = std::thread([s] { s->loop(); });
+  s->io = std::thread([s] { s->io_loop(); });
   *out = s;
   return FEMH_OK;
 }
@@ -539,6 +590,7 @@ void femh_server_destroy(femh_server* s) {
   }
   s->cv_work.notify_all();
   if (s->th.joinable()) s->th.join();
+  if (s->io.joinable()) s->io.join();
   for (auto& kv : s->all) delete kv.second;
   for (femh::Ctx* c : s->lanes) {
     (void)hipStreamSynchronize(c->stream);
