@@ -307,6 +307,20 @@ int femh_spmm_dev(femh_problem* prob, int32_t precision, int32_t ncols, const vo
  * femh_spmv_dev. */
 int femh_spmv_half_dev(femh_problem* prob, const void* x_dev, void* y_dev, int32_t reps, double* avg_seconds);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): Y = A X
+ * exactly as femh_spmm_dev with ncols = 64 (X, Y device arrays
+ * [n_unknowns][64] complex128, column fastest; the same kernel, the
+ * problem's tuned grid or, before any tuning, the default one, so Y is the
+ * same bit for bit), but the product's partial sums and scalar block live in
+ * a static device array of 4 MiB + 64 KiB that each GPU holds until the
+ * process ends, and the call allocates nothing.  Only ncols = 64 is taken
+ * (FEMH_E_INVALID otherwise): the narrower layouts need a staging copy.
+ * Every call on one GPU shares that GPU's array, so calls that overlap on
+ * one GPU (two threads, two streams) race: serialise them.  Returns after
+ * the product has completed on the context's stream; no timing. */
+int femh_spmm_noalloc_dev(femh_problem* prob, int32_t precision, int32_t ncols, const void* X_dev, void* Y_dev);
+
 /* The wide SpMM shape the batched solver uses for this problem: *kind = 0
  * FP64 vector FMAs (the only kind the autotuner times, over grid sizes, on
  * the problem's first wide product, with that product's matrix), 1

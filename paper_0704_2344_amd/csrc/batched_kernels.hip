@@ -619,6 +619,10 @@ __global__ void k_bcount_active(BatchScalars* sc, int ncols) {
   }
 }
 
+__global__ void k_product_scalars(BatchScalars* sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc->active = 1;
+}
+
 // [nrhs][n] column-major right-hand sides -> [n][LD] block layout (zero pad).
 __global__ void k_to_block(int64_t n, int ld, int nrhs, const double2* __restrict__ b, double2* __restrict__ B) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -738,6 +742,11 @@ hipError_t bmr_step(hipStream_t st, const PatternDev& pt, int64_t n, int ld, con
     hipLaunchKernelGGL(k_bred_mr<LD>, dim3(LD), dim3(kBT), 0, st, (const double*)partials, blocks, sc, plan);
     hipLaunchKernelGGL(k_bmr_apply<LD>, dim3(blocks), dim3(kBT), 0, st, n, X, R, P, Q, sc, plan);
   });
+  return hipGetLastError();
+}
+
+hipError_t product_scalars(hipStream_t st, BatchScalars* sc) {
+  hipLaunchKernelGGL(k_product_scalars, dim3(1), dim3(64), 0, st, sc);
   return hipGetLastError();
 }
 

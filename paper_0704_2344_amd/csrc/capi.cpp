@@ -26,6 +26,16 @@ int copy_msg(const std::string& m, char* msg, size_t n) {
   return 0;
 }
 
+// Static scratch of the allocation-free product (femh_spmm_noalloc_dev): the
+// per-workgroup, per-column partial sums the wide product kernel writes (at
+// most 2048 workgroups x 64 columns x 4 doubles) and one scalar block.  Each
+// device holds its own copy until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returned for that device.
+constexpr size_t kScratchPartials = (size_t)2048 * 64 * 4 * sizeof(double);
+constexpr size_t kScratchBytes = kScratchPartials + 65536;
+static_assert(sizeof(femh::BatchScalars) <= 65536, "scalar block exceeds its scratch slot");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct DevTmp {
   Ctx* c;
   void* p;
@@ -90,8 +100,13 @@ int femh_ctx_create(int device, const femh_allocator* alloc, void* hip_stream, f
     femh::set_error("device %d is %s; this library is built for gfx950 only", device, prop.gcnArchName);
     return FEMH_E_DEVICE;
   }
+  // this device's copy of the allocation-free product's scratch (set-up,
+  // once per context; the symbol's host-side name is not a device address)
+  void* scratch_ptr = nullptr;
+  FEMH_TRY_HIP(hipGetSymbolAddress(&scratch_ptr, HIP_SYMBOL(scratch)));
   femh_ctx* c = new femh_ctx();
   c->device = device;
+  c->scratch = scratch_ptr;
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   if (alloc && alloc->alloc && alloc->free) c->alloc = *alloc;
   if (hip_stream) {
@@ -401,6 +416,38 @@ int femh_spmm_dev(femh_problem* p, int32_t precision, int32_t ncols, const void*
     FEMH_TRY_HIP(hipMemcpy2DAsync(Y, (size_t)ncols * 16, yp.p, 64 * 16, (size_t)ncols * 16, (size_t)n,
                                   hipMemcpyDeviceToDevice, s));
   FEMH_TRY_HIP(hipStreamSynchronize(s));
+  return FEMH_OK;
+}
+
+int femh_spmm_noalloc_dev(femh_problem* p, int32_t precision, int32_t ncols, const void* X, void* Y) {
+  femh::clear_error();
+  if (!p || !X || !Y || (precision != FEMH_FP64 && precision != FEMH_MIXED_MATRIX)) {
+    femh::set_error("bad spmm arguments (precision FP64 or MIXED_MATRIX, X and Y non-NULL)");
+    return FEMH_E_INVALID;
+  }
+  if (ncols != 64) {
+    femh::set_error("the allocation-free product takes the [n_unknowns][64] layout only (got %d columns)", ncols);
+    return FEMH_E_INVALID;
+  }
+  Ctx* c = p->ctx;
+  if (!c->scratch) {
+    femh::set_error("the context has no scratch address for its device");
+    return FEMH_E_DEVICE;
+  }
+  FEMH_TRY_HIP(hipSetDevice(c->device));
+  // the problem's tuned shape if it has one, else the untuned default (no
+  // timing run: that would allocate events)
+  femh::BatchTile t = p->tile.kind >= 0 ? p->tile : femh::BatchTile{0, femh::k::batched_blocks_for(p->pat.nn, c->n_cu, 8)};
+  if (t.blocks < 8 || t.blocks > 2048) {
+    femh::set_error("product grid of %d workgroups exceeds the scratch (at most 2048)", t.blocks);
+    return FEMH_E_INVALID;
+  }
+  double* partials = reinterpret_cast<double*>(c->scratch);
+  femh::BatchScalars* sc = reinterpret_cast<femh::BatchScalars*>(reinterpret_cast<char*>(c->scratch) + kScratchPartials);
+  const double2* val64 = precision == FEMH_FP64 ? p->val64 : nullptr;
+  FEMH_TRY_HIP(femh::k::product_scalars(c->stream, sc));
+  FEMH_TRY_HIP(femh::k::bspmm(c->stream, p->pat, p->val32, val64, (const double2*)X, (double2*)Y, partials, sc, t));
+  FEMH_TRY_HIP(hipStreamSynchronize(c->stream));
   return FEMH_OK;
 }
 

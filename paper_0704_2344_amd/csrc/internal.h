@@ -152,6 +152,8 @@ hipError_t bmr_step(hipStream_t st, const PatternDev& pt, int64_t n, int ld, con
                     double2* R, const double2* P, double2* Q, double* partials, int blocks, BatchTile tile,
                     const BatchScalars* run_all, BatchScalars* sc, const BatchPlan* plan);
 hipError_t to_block(hipStream_t st, int64_t n, int ld, int nrhs, const double2* b, double2* B);
+// a scalar block that lets the products run (active = 1), written on the device
+hipError_t product_scalars(hipStream_t st, BatchScalars* sc);
 hipError_t from_block(hipStream_t st, int64_t n, int ld, int nrhs, const double2* X, double2* x);
 
 // Exclusive prefix sum of n int32 (n >= 0); *total (device) gets the sum.
@@ -296,6 +298,7 @@ struct Ctx {
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   void* pinned = nullptr;  // small pinned host buffer for scalar readback
   int64_t live_bytes = 0;
+  void* scratch = nullptr;  // this device's copy of the allocation-free product's static scratch
 
   void* dmalloc(size_t bytes);
   void dfree(void* p);

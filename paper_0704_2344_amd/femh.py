@@ -144,6 +144,7 @@ SIGNATURES = {
     "femh_spmv_dev": (C.c_int, [P, I32, P, P, I32, PD]),
     "femh_spmm_dev": (C.c_int, [P, I32, I32, P, P, I32, PD]),
     "femh_spmm_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
+    "femh_spmm_noalloc_dev": (C.c_int, [P, I32, I32, P, P]),
     "femh_spmv_half_dev": (C.c_int, [P, P, P, I32, PD]),
     "femh_spmm_set_tile": (C.c_int, [P, I32, I32]),
     "femh_bw_probe": (C.c_int, [P, I64, I32, PD]),
