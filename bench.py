@@ -46,7 +46,20 @@ HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E datasheet
 # 1 GiB copy probe (1 GiB read + 1 GiB written) in the same run.  Valid only
 # for the kernel source it was taken on: reported as null once that file
 # changes.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    "m32_sphere_shell_60": {
+        "kernel": "k_cocg_spmv_dot<double, float2>", "source": "paper_0704_2344_amd/csrc/krylov_kernels.hip",
+        "sha256": "ffa42cb1b3bf8ff9da2ad9e716f922cfdb9ab6d3cde3b9b1bc086cc8969dd63a",
+        "fetch_kib": 225810.49, "write_kib": 10129.70,
+        "copy_fetch_kib": 524291.47, "copy_write_kib": 1048576.03, "copy_bytes": 1 << 30,
+    },
+    "c128_sphere_shell_60": {
+        "kernel": "k_cocg_spmv_dot<double, double2>", "source": "paper_0704_2344_amd/csrc/krylov_kernels.hip",
+        "sha256": "ffa42cb1b3bf8ff9da2ad9e716f922cfdb9ab6d3cde3b9b1bc086cc8969dd63a",
+        "fetch_kib": 423813.98, "write_kib": 10150.82,
+        "copy_fetch_kib": 524291.47, "copy_write_kib": 1048576.03, "copy_bytes": 1 << 30,
+    },
+}
 
 
 def measured_traffic(key):
@@ -202,7 +215,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed headline steps (mixed precision)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cmp-steps", type=int, default=2, help="timed FP64 steps beside the headline")
+    ap.add_argument("--cmp-steps", type=int, default=2,
+                    help="timed FP64 steps beside the headline (0 skips FP64 and the complex64-vector solve)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip every leg but the headline")
     ap.add_argument("--extras", default="cube,hbm,batched,planes,serving",
@@ -275,16 +289,19 @@ def main():
     ctx.profile_read(reset=True)
     value, elapsed, lat, st_m = timed(step, F.FEMH_MIXED_MATRIX, 1e-6, args.steps)
     sec, cnt = ctx.profile_read(reset=True)
-    log(f"matrix-mixed {value:.3f} solves/s; {args.cmp_steps} FP64 steps")
-    fp_sps, fp_el, fp_lat, st_f = timed(step, F.FEMH_FP64, 1e-6, args.cmp_steps)
-    sec64, cnt64 = ctx.profile_read(reset=True)
-    ctx.profile(False)
     nn, nnzb = info["nn"], info["nnzb"]
-    log(f"FP64 {fp_sps:.3f} solves/s; one complex64-vector solve")
-    # the complex64-vector mode, once (it breaks down on this system)
-    t0 = time.perf_counter()
-    st_c64 = step(F.FEMH_MIXED, 1e-6, allow_fail=True)
-    t_c64 = time.perf_counter() - t0
+    fp_sps, fp_lat, st_f, st_c64, t_c64 = None, [float("nan")], None, None, None
+    sec64, cnt64 = [0.0] * 4, [0] * 4
+    if args.cmp_steps > 0:
+        log(f"matrix-mixed {value:.3f} solves/s; {args.cmp_steps} FP64 steps")
+        fp_sps, fp_el, fp_lat, st_f = timed(step, F.FEMH_FP64, 1e-6, args.cmp_steps)
+        sec64, cnt64 = ctx.profile_read(reset=True)
+        log(f"FP64 {fp_sps:.3f} solves/s; one complex64-vector solve")
+        # the complex64-vector mode, once (it breaks down on this system)
+        t0 = time.perf_counter()
+        st_c64 = step(F.FEMH_MIXED, 1e-6, allow_fail=True)
+        t_c64 = time.perf_counter() - t0
+    ctx.profile(False)
 
     result = {
         "metric": "block SpMV GB/s (% HBM peak); solves/s + p99 latency at 1e-6, mixed vs FP64",
@@ -309,17 +326,19 @@ def main():
         "p99_s": float(np.percentile(lat, 99)),
         "solve": {"iters": st_m["iters"], "reliable_updates": st_m["outer_iters"],
                   "rel_residual": st_m["rel_residual"], "solve_s": st_m["seconds"]},
-        "fp64": {"solves_per_s": fp_sps, "p50_s": float(np.percentile(fp_lat, 50)),
-                 "p99_s": float(np.percentile(fp_lat, 99)), "steps": args.cmp_steps, "iters": st_f["iters"],
-                 "rel_residual": st_f["rel_residual"]},
-        "mixed_vs_fp64": value / fp_sps,
-        "mixed_c64_vectors": {"status": st_c64["status"], "iters": st_c64["iters"],
-                              "rel_residual": st_c64["rel_residual"], "seconds": t_c64},
+        "fp64": None if st_f is None else {
+            "solves_per_s": fp_sps, "p50_s": float(np.percentile(fp_lat, 50)),
+            "p99_s": float(np.percentile(fp_lat, 99)), "steps": args.cmp_steps, "iters": st_f["iters"],
+            "rel_residual": st_f["rel_residual"]},
+        "mixed_vs_fp64": value / fp_sps if fp_sps else None,
+        "mixed_c64_vectors": None if st_c64 is None else {
+            "status": st_c64["status"], "iters": st_c64["iters"], "rel_residual": st_c64["rel_residual"],
+            "seconds": t_c64},
         "roofline": spmv_event_roofline(sec[3], cnt[3], nn, nnzb, 8, 16,
                                         "k_cocg_spmv_dot<double, float2> (complex64 block values, complex128 "
                                         "vectors, FP64 sums: q = A p and p^T q)", "m32_sphere_shell_60",
                                         "434 MB complex64 matrix, larger than the 256 MB Infinity Cache"),
-        "roofline_fp64_product": spmv_event_roofline(sec64[0], cnt64[0], nn, nnzb, 16, 16,
+        "roofline_fp64_product": None if not cnt64[0] else spmv_event_roofline(sec64[0], cnt64[0], nn, nnzb, 16, 16,
                                                      "k_cocg_spmv_dot<double> (complex128 block SpMV w = A z "
                                                      "+ z^T w)", "c128_sphere_shell_60",
                                                      "845 MB complex128 matrix"),
