@@ -23,7 +23,9 @@ Also on the same JSON line:
   spmv_hbm      block SpMV bandwidth on the headline matrix in every precision
   batched       the 40^3 PEC sphere with 64 right-hand sides as one batch
   planes        the mirror-symmetric 30^3 box whole and as its quarter
-  serving       a Poisson stream through the continuous-batching server
+  serving       the seeded request stream through the continuous-batching
+                server at 0.5, 0.8 and 1.0 of its measured capacity, FP64
+                and matrix-mixed, beside the plain FP64 solver
   cpu_baseline  the CPU oracle on a bounded sample of the headline workload,
                 one thread and all threads, with the host CPU model
 """
@@ -92,69 +94,122 @@ def spmm_bytes(nn, nnzb, ncols, s_val=16):
     return nnzb * (9 * s_val + 4) + 4 * (nn + 1) + 3 * nn * ncols * (16 + 16)
 
 
-def serving_leg(ctx, F, W, n_requests, rate, n_hi):
-    """Replay a Poisson request stream in real time through the server (two
-    precisions, each wave its own solve, and with a request's waves batched)
-    and through the plain FP64 solver one request at a time."""
-    reqs = W.serving_stream(n_requests=n_requests, rate_per_s=rate, seed=46, n_lo=10, n_hi=n_hi, nrhs_hi=4)
-    n_rhs = sum(len(r.waves) for r in reqs)
-    out = {"workload": (f"{n_requests} requests of the seeded serving stream (Poisson, {rate:g}/s), meshes n^3 "
-                        f"with n in [10, {n_hi}], 1-4 waves each ({n_rhs} right-hand sides), PEC box or sphere, "
-                        f"k0 in [pi, 4 pi] at 10 nodes per wavelength, rtol 1e-6")}
-    # warm the kernels and the allocator
-    srv = F.Server(ctx)
-    p0, w0 = reqs[0].problem, reqs[0].waves
-    t = srv.submit(p0, w0, precision=F.FEMH_FP64, rtol=1e-6)
-    srv.poll(t, len(w0), None, want_field=False)
-    srv.close()
-    for name, prec, batch in (("server_mixed_matrix", F.FEMH_MIXED_MATRIX, False),
-                              ("server_fp64", F.FEMH_FP64, False),
-                              ("server_mixed_matrix_batched", F.FEMH_MIXED_MATRIX, True),
-                              ("server_fp64_batched", F.FEMH_FP64, True)):
-        srv = F.Server(ctx, batch_rhs=batch)
-        t0 = time.perf_counter()
-        tickets = []
-        for r in reqs:
-            d = t0 + r.arrival_s - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            tickets.append(srv.submit(r.problem, r.waves, precision=prec, rtol=1e-6))
-        bad = 0
-        for r, tk in zip(reqs, tickets):
-            st, _, _ = srv.poll(tk, len(r.waves), None, want_field=False)
-            bad += st != F.FEMH_OK
-        el = time.perf_counter() - t0
-        rep = srv.report()
-        srv.close()
-        out[name] = {"requests_per_s": rep["requests_per_second"], "rhs_per_s": rep["rhs_per_second"],
-                     "p50_s": rep["p50_seconds"], "p99_s": rep["p99_seconds"], "failed": bad,
-                     "wall_s": el, "peak_resident_bytes": rep["peak_resident_bytes"]}
-    # plain FP64 solver, one request at a time in arrival order
-    import torch
-    lat = []
-    bad = 0
+SERVE_MODES = {
+    # name: (precision, batch a request's waves, inner_rtol (0 = the solver default))
+    "fp64_batched": ("FEMH_FP64", True, 0.0),
+    "mixed_matrix_batched": ("FEMH_MIXED_MATRIX", True, 0.0),
+    "fp64": ("FEMH_FP64", False, 0.0),
+    "mixed_matrix": ("FEMH_MIXED_MATRIX", False, 0.0),
+    "mixed_matrix_batched_inner1e-5": ("FEMH_MIXED_MATRIX", True, 1e-5),
+    "mixed_matrix_inner1e-5": ("FEMH_MIXED_MATRIX", False, 1e-5),
+}
+
+
+def _replay(F, ctx, reqs, arrivals, prec, batch, inner, label):
+    """Submit each request at its arrival time (seconds after the start),
+    then wait for all; the server's report gives latency percentiles."""
+    srv = F.Server(ctx, batch_rhs=batch)
     t0 = time.perf_counter()
-    first = None
-    for r in reqs:
-        d = t0 + r.arrival_s - time.perf_counter()
+    tickets = []
+    for r, a in zip(reqs, arrivals):
+        d = t0 + a - time.perf_counter()
         if d > 0:
             time.sleep(d)
-        if first is None:
-            first = time.perf_counter()
-        P = F.Problem(ctx, r.problem)
-        o = torch.zeros(P.grid_shape(len(r.waves)), dtype=torch.complex128, device="cuda")
-        _, st = P.solve_dev(r.waves, o, precision=F.FEMH_FP64, rtol=1e-6)
-        torch.cuda.synchronize()
-        P.close()
+        tickets.append(srv.submit(r.problem, r.waves, precision=prec, rtol=1e-6, inner_rtol=inner))
+    bad = 0
+    for i, (r, tk) in enumerate(zip(reqs, tickets)):
+        st, _, _ = srv.poll(tk, len(r.waves), None, want_field=False)
         bad += st != F.FEMH_OK
-        lat.append(time.perf_counter() - (t0 + r.arrival_s))
-    span = time.perf_counter() - first
-    out["plain_fp64_sequential"] = {"requests_per_s": n_requests / span, "rhs_per_s": n_rhs / span,
-                                    "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-                                    "failed": bad}
-    plain = out["plain_fp64_sequential"]["rhs_per_s"]
-    out["server_mixed_vs_plain_fp64"] = out["server_mixed_matrix"]["rhs_per_s"] / plain
-    out["server_mixed_batched_vs_plain_fp64"] = out["server_mixed_matrix_batched"]["rhs_per_s"] / plain
+        log(f"  {label}: request {i + 1}/{len(reqs)} (n = {r.problem.nx}, {len(r.waves)} waves) done at "
+            f"{time.perf_counter() - t0:.2f} s")
+    el = time.perf_counter() - t0
+    rep = srv.report()
+    srv.close()
+    n_rhs = sum(len(r.waves) for r in reqs)
+    return {"wall_s": el, "requests_per_s": len(reqs) / el, "rhs_per_s": n_rhs / el,
+            "p50_s": rep["p50_seconds"], "p99_s": rep["p99_seconds"], "failed": bad,
+            "peak_resident_bytes": rep["peak_resident_bytes"]}
+
+
+def serving_leg(ctx, F, W, n_requests, n_lo, n_hi, nrhs_hi, loads, modes, capacity=None):
+    """The seeded serving stream through the continuous-batching server.
+
+    Capacity is measured first: every request submitted at once to the FP64
+    server (each request's waves batched), requests/s over the whole span.
+    Then the same requests arrive as a Poisson stream at each load (a
+    fraction of that capacity, in requests/s) in real time, through each
+    server mode; every mode sees the same arrival times, so latency and
+    throughput compare at equal offered traffic.  The plain FP64 solver (one
+    request at a time: assembly, solve, field to host) is timed once per
+    request; its latencies at each load follow from those service times by
+    the first-in-first-out recursion finish_i = max(arrival_i, finish_(i-1))
+    + service_i, which is what a one-at-a-time solver does.  With no loads,
+    every mode gets the all-at-once run instead (its own capacity)."""
+    import torch
+
+    unknown = set(modes) - set(SERVE_MODES) - {"plain_fp64"}
+    if unknown:
+        raise SystemExit(f"unknown --serve-modes: {sorted(unknown)}")
+    reqs = W.serving_stream(n_requests=n_requests, rate_per_s=1.0, seed=46, n_lo=n_lo, n_hi=n_hi, nrhs_hi=nrhs_hi)
+    unit = np.array([r.arrival_s for r in reqs])     # arrivals of a rate-1 Poisson stream
+    n_rhs = sum(len(r.waves) for r in reqs)
+    unk = [3 * (r.problem.nx + 1) ** 3 for r in reqs]
+    out = {"workload": (f"{n_requests} requests of the seeded serving stream: meshes n^3 with n in [{n_lo}, {n_hi}] "
+                        f"(up to {max(unk)} grid unknowns), PEC box or sphere, k0 in [pi, 4 pi] at 10 nodes per "
+                        f"wavelength, 1-{nrhs_hi} waves each ({n_rhs} right-hand sides), FP64 relative residual "
+                        f"1e-6; " + ("Poisson arrivals at each load's rate" if loads else "all submitted at once")),
+           "loads": list(loads)}
+    # warm the kernels and the allocator on a small request
+    pw, ww = W.serving_request(np.random.default_rng(7), n_lo=10, n_hi=12, nrhs_hi=2)
+    for batch in (True, False):
+        srv = F.Server(ctx, batch_rhs=batch)
+        t = srv.submit(pw, ww, precision=F.FEMH_FP64, rtol=1e-6)
+        srv.poll(t, len(ww), None, want_field=False)
+        srv.close()
+    if capacity is None and loads:
+        sat = _replay(F, ctx, reqs, np.zeros(n_requests), F.FEMH_FP64, True, 0.0, "capacity (fp64_batched, all at once)")
+        capacity = sat["requests_per_s"]
+        out["saturated_fp64_batched"] = sat
+    out["capacity_requests_per_s"] = capacity
+    for name in modes:
+        if name == "plain_fp64":
+            continue
+        pn, batch, inner = SERVE_MODES[name]
+        if not loads:
+            out[f"saturated_{name}"] = _replay(F, ctx, reqs, np.zeros(n_requests), getattr(F, pn), batch, inner,
+                                               f"{name}, all at once")
+            continue
+        res = {}
+        for load in loads:
+            res[f"load_{load:g}"] = _replay(F, ctx, reqs, unit / (load * capacity), getattr(F, pn), batch, inner,
+                                            f"{name} at {load:g}x capacity")
+        out[f"server_{name}"] = res
+    if "plain_fp64" in modes:
+        service = []
+        for i, r in enumerate(reqs):
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            P = F.Problem(ctx, r.problem)
+            o = torch.zeros(P.grid_shape(len(r.waves)), dtype=torch.complex128, device="cuda")
+            _, st = P.solve_dev(r.waves, o, precision=F.FEMH_FP64, rtol=1e-6)
+            o.cpu()
+            P.close()
+            service.append(time.perf_counter() - s0)
+            log(f"  plain fp64: request {i + 1}/{len(reqs)} (n = {r.problem.nx}, {len(r.waves)} waves) "
+                f"{service[-1]:.3f} s")
+        service = np.array(service)
+        res = {"service_s_total": float(service.sum()), "capacity_requests_per_s": n_requests / service.sum()}
+        for load in loads:
+            arr = unit / (load * capacity)
+            fin = np.zeros(n_requests)
+            prev = 0.0
+            for i in range(n_requests):
+                prev = max(arr[i], prev) + service[i]
+                fin[i] = prev
+            lat = fin - arr
+            res[f"load_{load:g}"] = {"wall_s": float(fin[-1]), "rhs_per_s": n_rhs / float(fin[-1]),
+                                     "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99))}
+        out["plain_fp64_sequential"] = res
     return out
 
 
@@ -227,9 +282,16 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=60)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run the 1 GiB copy probe (the denominator of the traffic scale factor)")
-    ap.add_argument("--serve-requests", type=int, default=32)
-    ap.add_argument("--serve-rate", type=float, default=20.0)
-    ap.add_argument("--serve-n-hi", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-n-lo", type=int, default=10, help="smallest mesh n of the serving requests")
+    ap.add_argument("--serve-n-hi", type=int, default=24, help="largest mesh n of the serving requests")
+    ap.add_argument("--serve-nrhs-hi", type=int, default=16)
+    ap.add_argument("--serve-loads", default="0.5,0.8,1.0",
+                    help="offered loads, fractions of the measured capacity ('' = each mode all at once)")
+    ap.add_argument("--serve-modes", default="fp64_batched,mixed_matrix_batched,plain_fp64",
+                    help="comma-separated subset of " + ",".join(list(SERVE_MODES) + ["plain_fp64"]))
+    ap.add_argument("--serve-capacity", type=float, default=0.0,
+                    help="requests/s to take as the capacity instead of measuring it (0 = measure)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (asked for --gpus {args.gpus}); the multi-GPU path is a design "
@@ -484,7 +546,10 @@ def main():
     if "serving" in legs:
         log("leg serving")
     if "serving" in legs and args.serve_requests > 0:
-        result["serving"] = serving_leg(ctx, F, W, args.serve_requests, args.serve_rate, args.serve_n_hi)
+        result["serving"] = serving_leg(ctx, F, W, args.serve_requests, args.serve_n_lo, args.serve_n_hi,
+                                        args.serve_nrhs_hi, [float(x) for x in args.serve_loads.split(",") if x],
+                                        [x for x in args.serve_modes.split(",") if x],
+                                        args.serve_capacity or None)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one thread, then all threads)")

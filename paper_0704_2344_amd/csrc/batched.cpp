@@ -462,6 +462,9 @@ BatchStepper* batch_stepper_create(Problem* P, int nrhs, const double2* b, doubl
 int batch_stepper_step(BatchStepper* s, bool* progress) { return s->step(progress); }
 bool batch_stepper_done(const BatchStepper* s) { return s->phase == BatchStepper::DONE; }
 void batch_stepper_wait(BatchStepper* s) { s->wait(); }
+bool batch_stepper_iterating(const BatchStepper* s) {
+  return s->phase == BatchStepper::ITER || s->phase == BatchStepper::DONE;
+}
 int batch_stepper_stats(const BatchStepper* s, femh_solve_stats* st) { return s->fill_stats(st); }
 void batch_stepper_destroy(BatchStepper* s) { delete s; }
 

@@ -383,6 +383,7 @@ BatchStepper* batch_stepper_create(Problem* P, int nrhs, const double2* b, doubl
 int batch_stepper_step(BatchStepper* s, bool* progress);
 bool batch_stepper_done(const BatchStepper* s);
 void batch_stepper_wait(BatchStepper* s);
+bool batch_stepper_iterating(const BatchStepper* s);  // past its set-up phases (iterating or done)
 int batch_stepper_stats(const BatchStepper* s, femh_solve_stats* st);  // first failing status
 void batch_stepper_destroy(BatchStepper* s);
 

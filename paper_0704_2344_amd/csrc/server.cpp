@@ -1,13 +1,20 @@
 // Continuous-batching request loop.
 //
-// A stepping thread and a set-up thread share a few internal contexts, one
-// HIP stream each (default priority; device memory from hipMalloc).
+// A stepping thread and a set-up thread share the work; every admitted
+// request gets an internal context of its own with its own HIP stream
+// (default priority; device memory from hipMalloc), and at any time exactly
+// one of the two threads works on that stream: the set-up thread until the
+// request is set up, the stepping thread while it iterates, the set-up
+// thread again once it is handed back.  A stream is therefore never captured
+// by one thread while the other enqueues work on it.
 // Submitted requests wait in a FIFO queue; the stepping thread admits them
 // (first fit within a small window) as long as a slot is free and their
 // estimated device footprint fits the budget, and hands each admitted
-// request to the set-up thread, which assembles its problem on the next
-// stream and creates one solver state machine per right-hand side (or per
-// group of up to four).  Every round the stepping thread advances all
+// request to the set-up thread, which assembles its problem on the
+// request's stream and creates one solver state machine per right-hand
+// side (or per group of up to four; a group's chunk of iterations is
+// captured into a graph there, by the set-up thread).  Every round the
+// stepping thread advances all
 // resident, set-up right-hand sides of all requests (each queues its next
 // chunk of iterations without waiting), so requests of different sizes
 // overlap on the device; a request whose columns have all finished (or that
@@ -69,7 +76,6 @@ struct Request {
 
 struct femh_server {
   femh::Ctx* base = nullptr;
-  std::vector<femh::Ctx*> lanes;
   int64_t budget = 0;
   int max_slots = 32;
   int chunk = 32;
@@ -96,7 +102,6 @@ struct femh_server {
   int64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, rejected = 0, rhs_completed = 0;
   std::vector<double> latencies;
   double t_first_submit = -1, t_last_done = -1;
-  int next_lane = 0;
 
   void loop();
   void io_loop();
@@ -107,6 +112,36 @@ struct femh_server {
 };
 
 namespace {
+
+// A request's own context: the server device, a non-blocking stream and a
+// small pinned buffer for scalar readbacks.
+femh::Ctx* lane_create(const femh::Ctx* base) {
+  femh::Ctx* c = new femh::Ctx();
+  c->device = base->device;
+  c->n_cu = base->n_cu;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return nullptr;
+  }
+  if (hipHostMalloc(&c->pinned, 16384, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+    return nullptr;
+  }
+  c->own_stream = true;
+  return c;
+}
+
+void lane_destroy(femh::Ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  (void)hipStreamDestroy(c->stream);
+  (void)hipHostFree(c->pinned);
+  delete c;
+}
 
 void release(Request* r) {
   for (femh::Stepper* s : r->steps) femh::stepper_destroy(s);
@@ -121,6 +156,8 @@ void release(Request* r) {
   r->b = r->x = nullptr;
   delete r->P;
   r->P = nullptr;
+  lane_destroy(r->lane);
+  r->lane = nullptr;
 }
 
 }  // namespace
@@ -159,8 +196,11 @@ void femh_server::admit_locked(std::vector<Request*>& admitted) {
 }
 
 int femh_server::setup(Request* r) {
-  r->lane = lanes[next_lane];
-  next_lane = (next_lane + 1) % (int)lanes.size();
+  r->lane = lane_create(base);
+  if (!r->lane) {
+    femh::set_error("request stream creation failed");
+    return FEMH_E_DEVICE;
+  }
   femh::Ctx* c = r->lane;
   (void)hipSetDevice(c->device);
   femh_problem_desc d = r->desc;
@@ -202,6 +242,14 @@ int femh_server::setup(Request* r) {
       if (!s) return FEMH_E_OOM;
       r->bsteps.push_back(s);
       r->bfirst.push_back(g);
+      // bring the group to its iterations here, so its graph is captured
+      // by this thread, before the stepping thread takes the stream over
+      while (!femh::batch_stepper_iterating(s)) {
+        bool prog = false;
+        const int st = femh::batch_stepper_step(s, &prog);
+        if (st != FEMH_OK) return st;
+        if (!prog) femh::batch_stepper_wait(s);
+      }
     }
     return FEMH_OK;
   }
@@ -422,26 +470,6 @@ int femh_server_create(femh_ctx* ctx_, const femh_server_opts* opts, femh_server
   s->max_slots = o.max_slots > 0 ? o.max_slots : 32;
   s->chunk = o.chunk_iters > 0 ? o.chunk_iters : 32;
   s->batch_rhs = o.batch_rhs != 0;
-  const int nlanes = 4;
-  for (int i = 0; i < nlanes; ++i) {
-    femh::Ctx* c = new femh::Ctx();
-    c->device = ctx->device;
-    c->n_cu = ctx->n_cu;
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
-        hipHostMalloc(&c->pinned, 16384, hipHostMallocDefault) != hipSuccess) {
-      delete c;
-      for (femh::Ctx* l : s->lanes) {
-        (void)hipStreamDestroy(l->stream);
-        (void)hipHostFree(l->pinned);
-        delete l;
-      }
-      delete s;
-      femh::set_error("server stream creation failed");
-      return FEMH_E_DEVICE;
-    }
-    c->own_stream = true;
-    s->lanes.push_back(c);
-  }
   s->th = std::thread([s] { s->loop(); });
   s->io = std::thread([s] { s->io_loop(); });
   *out = s;
@@ -592,12 +620,6 @@ void femh_server_destroy(femh_server* s) {
   if (s->th.joinable()) s->th.join();
   if (s->io.joinable()) s->io.join();
   for (auto& kv : s->all) delete kv.second;
-  for (femh::Ctx* c : s->lanes) {
-    (void)hipStreamSynchronize(c->stream);
-    (void)hipStreamDestroy(c->stream);
-    (void)hipHostFree(c->pinned);
-    delete c;
-  }
   delete s;
 }
 

@@ -222,3 +222,35 @@ def test_served_fields_match_the_oracle(ctx, prec, batch):
     rep = srv.report()
     assert rep["failed"] == 0 and rep["completed"] == len(reqs)
     srv.close()
+
+
+def test_many_batched_requests_at_once_match_batched_solves(ctx):
+    """Twenty-four requests with batched waves submitted together, so that
+    set-up (assembly, graph capture) of some overlaps the iterations of
+    others: every request succeeds, and each group of up to four waves is
+    bit-identical to femh_solve_batched_dev on the same waves."""
+    import torch
+    rng = np.random.default_rng(17)
+    reqs = [W.serving_request(rng, n_lo=8, n_hi=16, nrhs_hi=9) for _ in range(24)]
+    opts = dict(precision=F.FEMH_FP64, rtol=1e-6, check_every=16)
+    srv = F.Server(ctx, max_slots=16, chunk_iters=16, batch_rhs=True)
+    tickets = [srv.submit(p, w, **opts) for p, w in reqs]
+    fields = []
+    for (p, w), t in zip(reqs, tickets):
+        st, H, stats = srv.poll(t, len(w), _shape(p, len(w)))
+        assert st == F.FEMH_OK, stats
+        fields.append(H)
+    rep = srv.report()
+    assert rep["completed"] == len(reqs) and rep["failed"] == 0
+    srv.close()
+    for (p, w), H in zip(reqs, fields):
+        P = F.Problem(ctx, p)
+        for g in range(0, len(w), 4):
+            ww = w[g:g + 4]
+            out = torch.zeros(P.grid_shape(len(ww)), dtype=torch.complex128, device="cuda")
+            # a request of two or more waves runs every group (a last group
+            # of one included) through the batched solver
+            s, st = P.solve_dev(ww, out, batched=len(w) >= 2, **opts)
+            assert st == F.FEMH_OK, s
+            np.testing.assert_array_equal(out.cpu().numpy(), H[g:g + 4])
+        P.close()
