@@ -116,10 +116,12 @@ def _replay(F, ctx, reqs, arrivals, prec, batch, inner, label):
         if d > 0:
             time.sleep(d)
         tickets.append(srv.submit(r.problem, r.waves, precision=prec, rtol=1e-6, inner_rtol=inner))
-    bad = 0
+    bad = []
     for i, (r, tk) in enumerate(zip(reqs, tickets)):
-        st, _, _ = srv.poll(tk, len(r.waves), None, want_field=False)
-        bad += st != F.FEMH_OK
+        st, _, stats = srv.poll(tk, len(r.waves), None, want_field=False)
+        if st != F.FEMH_OK:
+            bad.append({"request": i, "n": r.problem.nx, "waves": len(r.waves), "status": st,
+                        "iters": [s["iters"] for s in stats], "rel_residual": [s["rel_residual"] for s in stats]})
         log(f"  {label}: request {i + 1}/{len(reqs)} (n = {r.problem.nx}, {len(r.waves)} waves) done at "
             f"{time.perf_counter() - t0:.2f} s")
     el = time.perf_counter() - t0
@@ -127,7 +129,7 @@ def _replay(F, ctx, reqs, arrivals, prec, batch, inner, label):
     srv.close()
     n_rhs = sum(len(r.waves) for r in reqs)
     return {"wall_s": el, "requests_per_s": len(reqs) / el, "rhs_per_s": n_rhs / el,
-            "p50_s": rep["p50_seconds"], "p99_s": rep["p99_seconds"], "failed": bad,
+            "p50_s": rep["p50_seconds"], "p99_s": rep["p99_seconds"], "failed": len(bad), "failures": bad,
             "peak_resident_bytes": rep["peak_resident_bytes"]}
 
 
