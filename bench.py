@@ -105,6 +105,17 @@ SERVE_MODES = {
 }
 
 
+def fifo_finish_times(arrivals, service):
+    """Finish times of a one-at-a-time server taking requests in arrival
+    order: finish_i = max(arrival_i, finish_(i-1)) + service_i."""
+    fin = np.zeros(len(arrivals))
+    prev = 0.0
+    for i, (a, s) in enumerate(zip(arrivals, service)):
+        prev = max(float(a), prev) + float(s)
+        fin[i] = prev
+    return fin
+
+
 def _replay(F, ctx, reqs, arrivals, prec, batch, inner, label):
     """Submit each request at its arrival time (seconds after the start),
     then wait for all; the server's report gives latency percentiles."""
@@ -203,11 +214,7 @@ def serving_leg(ctx, F, W, n_requests, n_lo, n_hi, nrhs_hi, loads, modes, capaci
         res = {"service_s_total": float(service.sum()), "capacity_requests_per_s": n_requests / service.sum()}
         for load in loads:
             arr = unit / (load * capacity)
-            fin = np.zeros(n_requests)
-            prev = 0.0
-            for i in range(n_requests):
-                prev = max(arr[i], prev) + service[i]
-                fin[i] = prev
+            fin = fifo_finish_times(arr, service)
             lat = fin - arr
             res[f"load_{load:g}"] = {"wall_s": float(fin[-1]), "rhs_per_s": n_rhs / float(fin[-1]),
                                      "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99))}

@@ -75,3 +75,20 @@ def test_multi_gpu_request_is_refused():
                        capture_output=True, text=True, timeout=300, cwd=ROOT)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_fifo_finish_times_of_a_one_at_a_time_solver():
+    """The plain solver's latencies under load come from its service times by
+    the first-in-first-out recursion; checked by hand on a queue that drains
+    and refills: idle gap, back-to-back arrivals, a long job holding later ones."""
+    arr = [0.0, 0.5, 0.6, 5.0, 5.1]
+    svc = [1.0, 1.0, 2.0, 0.5, 0.1]
+    fin = bench.fifo_finish_times(arr, svc)
+    assert list(fin) == [1.0, 2.0, 4.0, 5.5, 5.6]
+    assert list(fin - arr) == [1.0, 1.5, 3.4, 0.5, 0.5]
+
+
+def test_unknown_serving_mode_is_refused():
+    import pytest
+    with pytest.raises(SystemExit):
+        bench.serving_leg(None, None, None, 1, 10, 12, 1, [0.5], ["no_such_mode"])
