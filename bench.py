@@ -291,9 +291,9 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=60)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run the 1 GiB copy probe (the denominator of the traffic scale factor)")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-n-lo", type=int, default=10, help="smallest mesh n of the serving requests")
-    ap.add_argument("--serve-n-hi", type=int, default=24, help="largest mesh n of the serving requests")
+    ap.add_argument("--serve-n-hi", type=int, default=26, help="largest mesh n of the serving requests")
     ap.add_argument("--serve-nrhs-hi", type=int, default=16)
     ap.add_argument("--serve-loads", default="0.5,0.8,1.0",
                     help="offered loads, fractions of the measured capacity ('' = each mode all at once)")
