@@ -544,7 +544,9 @@ femh_solve_opts opts_with_defaults(const femh_solve_opts* o) {
   femh_solve_opts r{};
   if (o) r = *o;
   if (r.rtol <= 0.0) r.rtol = 1e-6;
-  if (r.max_iter <= 0) r.max_iter = 50000;
+  // COCG-Jacobi's iteration count grows with the box size in wavelengths:
+  // a 6.4-wavelength serving box (64^3) already needs 48 000 in FP64
+  if (r.max_iter <= 0) r.max_iter = 200000;
   // complex64 recurrences can only shrink their residual about one decade
   // before its rounding dominates; an FP64 recurrence with a complex64 matrix
   // can go much further between reliable updates
