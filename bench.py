@@ -219,6 +219,14 @@ def serving_leg(ctx, F, W, n_requests, n_lo, n_hi, nrhs_hi, loads, modes, capaci
             res[f"load_{load:g}"] = {"wall_s": float(fin[-1]), "rhs_per_s": n_rhs / float(fin[-1]),
                                      "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99))}
         out["plain_fp64_sequential"] = res
+    # throughput of each server mode against the plain solver on the same
+    # arrivals at the highest load
+    if loads and "plain_fp64_sequential" in out:
+        top = f"load_{max(loads):g}"
+        plain = out["plain_fp64_sequential"][top]["rhs_per_s"]
+        for name in modes:
+            if name != "plain_fp64" and f"server_{name}" in out:
+                out[f"server_{name}_vs_plain_fp64"] = out[f"server_{name}"][top]["rhs_per_s"] / plain
     return out
 
 
