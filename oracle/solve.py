@@ -9,7 +9,12 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
   x^T y replaces the inner product (the incomplete-Cholesky recurrences of
   eq. (5) likewise carry no conjugation), stopping on the Hermitian 2-norm
   of the recursive residual.  Diagonal preconditioning (section 3.1.5.1):
-  z = D^-1 r with D the diagonal of the matrix.  x0 = 0.
+  z = D^-1 r with D the diagonal of the matrix.  x0 = 0;
+* pcocg        -- the same recurrence with any preconditioner z = M^-1 r;
+* bic0_factor, bic0_apply -- the block incomplete Cholesky preconditioner of
+  sections 3.1.5.2-3.1.5.3: eq. (5)'s incomplete factor on the diagonal
+  blocks of B consecutive nodes, applied by the forward and back
+  substitution of eq. (6).
 """
 from __future__ import annotations
 
@@ -51,12 +56,19 @@ def cocg(A, b, rtol=1e-10, maxiter=10000, jacobi=True, breakdown_tol=1e-14):
     breakdown_tol times the squared norms that bound it."""
     b = np.asarray(b, dtype=np.complex128)
     dinv = 1.0 / A.diagonal() if jacobi else np.ones_like(b)
+    return pcocg(A, b, lambda r: dinv * r, rtol, maxiter, breakdown_tol)
+
+
+def pcocg(A, b, apply_m, rtol=1e-10, maxiter=10000, breakdown_tol=1e-14):
+    """COCG with the preconditioner z = apply_m(r), M complex-symmetric
+    (the recurrence of section 3.1.5 with the bilinear form x^T y)."""
+    b = np.asarray(b, dtype=np.complex128)
     bnorm = np.linalg.norm(b)
     x = np.zeros_like(b)
     if bnorm == 0.0:
         return CocgResult(x, 0, 0.0, False, [0.0])
     r = b.copy()
-    z = dinv * r
+    z = apply_m(r)
     p = z.copy()
     rho = bilinear(r, z)
     hist = [1.0]
@@ -74,7 +86,7 @@ def cocg(A, b, rtol=1e-10, maxiter=10000, jacobi=True, breakdown_tol=1e-14):
         hist.append(rel)
         if rel <= rtol:
             return CocgResult(x, k, rel, False, hist)
-        z = dinv * r
+        z = apply_m(r)
         rho_new = bilinear(r, z)
         if abs(rho_new) <= breakdown_tol * np.linalg.norm(r) * np.linalg.norm(z):
             return CocgResult(x, k, rel, True, hist)
@@ -82,6 +94,52 @@ def cocg(A, b, rtol=1e-10, maxiter=10000, jacobi=True, breakdown_tol=1e-14):
         rho = rho_new
         p = z + beta * p
     return CocgResult(x, maxiter, hist[-1], False, hist)
+
+
+def bic0_factor(A, nodes_per_block):
+    """Block incomplete Cholesky (sections 3.1.5.2-3.1.5.3).  The unknowns
+    are cut into blocks of B = nodes_per_block consecutive nodes (3 B
+    unknowns; the last block may be shorter) and the couplings between
+    blocks are dropped, as each processor of the paper keeps only its
+    diagonal block.  Each block gets the incomplete factor of eq. (5) on its
+    own lower pattern, column by column and without conjugation (A is
+    complex-symmetric, A ~ L L^T).  The pattern is A's stored structure (all
+    nine entries of the 3x3 block of every pair of nodes that share an
+    element), not its nonzero values: summation leaves some entries that are
+    zero in exact arithmetic at +-1e-18 on one side of the diagonal only.
+        l_jj = sqrt(a_jj - sum_{k<j} l_jk^2)
+        l_ij = (a_ij - sum_{k<j} l_ik l_jk) / l_jj,  i > j, (i, j) stored
+    (the principal complex square root).  Returns L (CSR, lower triangular,
+    block diagonal)."""
+    A = sp.csr_matrix(A)
+    S = A.copy()
+    S.data = np.ones_like(S.data)
+    n = A.shape[0]
+    size = 3 * nodes_per_block
+    rows, cols, vals = [], [], []
+    for b0 in range(0, n, size):
+        b1 = min(b0 + size, n)
+        blk = A[b0:b1, b0:b1].toarray()
+        keep = np.tril(S[b0:b1, b0:b1].toarray() != 0)
+        L = np.where(keep, blk, 0.0).astype(np.complex128)
+        m = b1 - b0
+        for j in range(m):
+            L[j, j] = np.sqrt(L[j, j] - np.sum(L[j, :j] * L[j, :j]))
+            for i in range(j + 1, m):
+                if keep[i, j]:
+                    L[i, j] = (L[i, j] - np.sum(L[i, :j] * L[j, :j])) / L[j, j]
+        r, c = np.nonzero(keep)
+        rows.append(r + b0)
+        cols.append(c + b0)
+        vals.append(L[r, c])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+
+def bic0_apply(L, r):
+    """z = (L L^T)^-1 r: forward substitution L y = r, then back substitution
+    L^T z = y (eq. (6))."""
+    y = spla.spsolve_triangular(sp.csr_matrix(L), np.asarray(r, np.complex128), lower=True)
+    return spla.spsolve_triangular(sp.csr_matrix(L.T), y, lower=False)
 
 
 def residual(A, x, b):

@@ -10,6 +10,7 @@ import math
 import os
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 import workloads as W
@@ -568,3 +569,59 @@ def test_bsr_blocks_and_grid_scatter_are_lossless():
     assert H.shape == (1, p.nz + 1, p.ny + 1, p.nx + 1, 3)
     np.testing.assert_array_equal(H[0][mesh.node_active].reshape(-1), x)
     assert np.all(H[0][~mesh.node_active] == 0)
+
+
+def test_bic0_on_a_full_pattern_is_the_complex_symmetric_cholesky_factor():
+    """With every entry in the pattern, eq. (5)'s incomplete factor is the
+    exact complex-symmetric Cholesky factor: L L^T (not L L^H) = A."""
+    rng = np.random.default_rng(3)
+    n = 12
+    M = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = M @ M.T + 10 * n * np.eye(n)
+    L = solve.bic0_factor(sp.csr_matrix(A), n // 3).toarray()
+    assert np.all(np.triu(L, 1) == 0)
+    np.testing.assert_allclose(L @ L.T, A, rtol=0, atol=1e-12 * abs(A).max())
+    assert np.all(np.diag(L).real > 0)           # principal square roots
+    assert abs(L @ L.conj().T - A).max() > 1e-3 * abs(A).max()
+
+
+@pytest.mark.parametrize("nodes_per_block", [1, 8, 64])
+def test_bic0_is_exact_on_its_pattern_and_stays_inside_blocks(nodes_per_block):
+    """Incomplete Cholesky's defining property: (L L^T)_ij = a_ij at every
+    stored (i, j) inside a block; L has no entry outside the blocks of B
+    consecutive nodes and none above the diagonal.  B = 1 keeps only each
+    node's 3x3 diagonal block, whose factor is then exact."""
+    p, _ = W.pec_sphere_shell(n=6, radius=0.15, shell=0.06, seed=2)
+    A = fem.assemble(p).tocsr()
+    L = solve.bic0_factor(A, nodes_per_block)
+    size = 3 * nodes_per_block
+    Lc = L.tocoo()
+    assert np.all(Lc.row // size == Lc.col // size) and np.all(Lc.row >= Lc.col)
+    S = A.copy()
+    S.data = np.ones_like(S.data)
+    Sc = S.tocoo()
+    inside = Sc.row // size == Sc.col // size
+    LL = (L @ L.T).tocsr()
+    diff = np.asarray(LL[Sc.row[inside], Sc.col[inside]]).ravel() - np.asarray(A[Sc.row[inside], Sc.col[inside]]).ravel()
+    assert abs(diff).max() <= 1e-13 * abs(A).max()
+    assert L.nnz == (np.count_nonzero(inside) + A.shape[0]) // 2
+
+
+def test_bic0_apply_solves_with_l_lt_and_pcocg_reaches_the_lu_solution():
+    p, w = W.pec_sphere_shell(n=6, radius=0.15, shell=0.06, seed=2)
+    A = fem.assemble(p).tocsr()
+    b = fem.rhs(p, w)[:, 0]
+    L = solve.bic0_factor(A, 16)
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    z = solve.bic0_apply(L, r)
+    assert np.linalg.norm((L @ (L.T @ z)) - r) <= 1e-12 * np.linalg.norm(r)
+    res = solve.pcocg(A, b, lambda v: solve.bic0_apply(L, v), rtol=1e-12, maxiter=2000)
+    x = solve.dense_solve(A, b)
+    assert not res.breakdown and res.rel_res <= 1e-12
+    assert np.linalg.norm(res.x - x) <= 1e-9 * np.linalg.norm(x)
+    # the same recurrence with Jacobi is the oracle's COCG, iterate for iterate
+    d = 1.0 / A.diagonal()
+    a = solve.pcocg(A, b, lambda v: d * v, rtol=1e-10, maxiter=2000)
+    c = solve.cocg(A, b, rtol=1e-10, maxiter=2000)
+    assert a.iters == c.iters and np.array_equal(a.x, c.x)
