@@ -85,7 +85,19 @@ typedef enum { FEMH_FP64 = 0,          /* complex128 matrix and Krylov vectors *
                                           reliable updates against the FP64 matrix */ } femh_precision;
 
 typedef enum { FEMH_PRECOND_JACOBI = 0,  /* z = D^-1 r, D = diag(A) (section 3.1.5.1) */
-               FEMH_PRECOND_NONE = 1 } femh_precond;
+               FEMH_PRECOND_NONE = 1,
+               FEMH_PRECOND_BIC0 = 2     /* block incomplete Cholesky (sections 3.1.5.2-3.1.5.3): the
+                                            unknowns of precond_block consecutive nodes form a block,
+                                            couplings between blocks are dropped, and each block keeps
+                                            eq. (5)'s complex-symmetric IC(0) factor L L^T on the lower part
+                                            of its 3x3-block pattern; z = (L L^T)^-1 r by eq. (6)'s forward
+                                            and back substitution.  FEMH_FP64 single right-hand-side
+                                            solves only (femh_solve, femh_solve_dev, femh_solve_rhs_dev,
+                                            and servers without batch_rhs); the other precisions and the
+                                            batched solver return FEMH_E_INVALID.  The factor is built on
+                                            the device at the first such solve and kept with the problem
+                                            (FEMH_E_BREAKDOWN if a pivot vanishes). */
+} femh_precond;
 
 /* Device memory provider.  alloc returns a device pointer of at least
  * `bytes` bytes (NULL on failure) usable on the context's stream; free
@@ -124,6 +136,7 @@ typedef struct {
   int32_t precond;       /* femh_precond; default Jacobi */
   double rtol;           /* stop at ||b - A x||_2 <= rtol ||b||_2 (FP64 true residual); default 1e-6 */
   int32_t max_iter;      /* Krylov iterations in total (inner ones for MIXED); default 200000 */
+  int32_t precond_block; /* FEMH_PRECOND_BIC0: nodes per block, 1..512; default 64 (ignored otherwise) */
   double inner_rtol;     /* MIXED*: residual reduction between reliable updates; default 0.1
                             (FEMH_MIXED), 1e-3 (FEMH_MIXED_MATRIX) */
   int32_t max_outer;     /* MIXED: refinement steps; default 20 */
@@ -271,6 +284,18 @@ int femh_export_rhs(femh_problem* prob, int32_t nrhs, const femh_plane_wave* wav
 
 /* Jacobi diagonal inverse, host buffer [n_unknowns] complex128. */
 int femh_export_jacobi(const femh_problem* prob, femh_c128* dinv);
+
+/* The factor L of FEMH_PRECOND_BIC0 for blocks of nodes_per_block nodes
+ * (eq. (5) inside each block), built on the device if the problem does not
+ * hold it yet: scalar CSR over the n_unknowns rows, row_ptr[n_unknowns + 1],
+ * col_idx[nnz] and vals[nnz] complex128, columns ascending within a row and
+ * the diagonal entry last.  *nnz receives the entry count; with row_ptr,
+ * col_idx and vals all NULL only the count is returned (call once to size
+ * the buffers, then again to fill them).  Host pointers.  Errors:
+ * FEMH_E_INVALID (nodes_per_block outside 1..512, NULL prob or nnz),
+ * FEMH_E_BREAKDOWN (a pivot vanished or is not finite), FEMH_E_OOM. */
+int femh_export_bic0(femh_problem* prob, int32_t nodes_per_block, int64_t* nnz, int32_t* row_ptr, int32_t* col_idx,
+                     femh_c128* vals);
 
 /* y = A x on device vectors of n_unknowns complex entries: complex128 for
  * FEMH_FP64, complex64 with FP32 accumulation for FEMH_MIXED, the complex64

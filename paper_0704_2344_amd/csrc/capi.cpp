@@ -58,16 +58,11 @@ static int require_mesh(const femh_problem* prob) {
   return FEMH_OK;
 }
 
-static int check_opts(const femh_solve_opts& o) {
-  if (o.precision != FEMH_FP64 && o.precision != FEMH_MIXED && o.precision != FEMH_MIXED_MATRIX) {
-    femh::set_error("unknown precision %d", o.precision);
-    return FEMH_E_INVALID;
-  }
-  if (o.precond != FEMH_PRECOND_JACOBI && o.precond != FEMH_PRECOND_NONE) {
-    femh::set_error("unknown preconditioner %d", o.precond);
-    return FEMH_E_INVALID;
-  }
-  return FEMH_OK;
+static int check_opts(const femh_solve_opts& o, bool batched = false) {
+  std::string m;
+  const int st = femh::check_solve_opts(o, batched, m);
+  if (st != FEMH_OK) femh::set_error("%s", m.c_str());
+  return st;
 }
 
 extern "C" {
@@ -342,10 +337,7 @@ int femh_solve_batched_dev(femh_problem* prob, int32_t nrhs, const femh_plane_wa
   // both recurrences are FP64: reliable updates every three decades
   if (ob.inner_rtol <= 0.0) ob.inner_rtol = 1e-3;
   const femh_solve_opts o = femh::opts_with_defaults(&ob);
-  if (o.precond != FEMH_PRECOND_JACOBI && o.precond != FEMH_PRECOND_NONE) {
-    femh::set_error("unknown preconditioner %d", o.precond);
-    return FEMH_E_INVALID;
-  }
+  FEMH_TRY(check_opts(o, true));
   Ctx* c = prob->ctx;
   FEMH_TRY_HIP(hipSetDevice(c->device));
   const int64_t n = 3 * (int64_t)prob->pat.nn;
@@ -535,6 +527,26 @@ int femh_export_jacobi(const femh_problem* p, femh_c128* dinv) {
   }
   FEMH_TRY_HIP(hipMemcpyAsync(dinv, p->dinv64, 48 * (size_t)p->pat.nn, hipMemcpyDeviceToHost, p->ctx->stream));
   FEMH_TRY_HIP(hipStreamSynchronize(p->ctx->stream));
+  return FEMH_OK;
+}
+
+int femh_export_bic0(femh_problem* p, int32_t nodes_per_block, int64_t* nnz, int32_t* row_ptr, int32_t* col_idx,
+                     femh_c128* vals) {
+  femh::clear_error();
+  if (!p || !nnz) {
+    femh::set_error("prob and nnz must not be NULL");
+    return FEMH_E_INVALID;
+  }
+  FEMH_TRY_HIP(hipSetDevice(p->ctx->device));
+  FEMH_TRY(femh::ensure_bic(p, nodes_per_block));
+  const int64_t n = 3 * (int64_t)p->pat.nn;
+  const int64_t nz = p->bic_nnz_l;
+  *nnz = nz;
+  hipStream_t s = p->ctx->stream;
+  if (row_ptr) FEMH_TRY_HIP(hipMemcpyAsync(row_ptr, p->bic.lrp, 4 * (size_t)(n + 1), hipMemcpyDeviceToHost, s));
+  if (col_idx) FEMH_TRY_HIP(hipMemcpyAsync(col_idx, p->bic.lcol, 4 * (size_t)nz, hipMemcpyDeviceToHost, s));
+  if (vals) FEMH_TRY_HIP(hipMemcpyAsync(vals, p->bic.lval, 16 * (size_t)nz, hipMemcpyDeviceToHost, s));
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
   return FEMH_OK;
 }
 

@@ -63,6 +63,23 @@ struct PatternDev {
   const int32_t* row_order;  // [nn] block-row order of the wide SpMM, or null (built on its first use)
 };
 
+// Block incomplete Cholesky factor (blocks of nodes_per_block consecutive
+// nodes): L as scalar CSR (columns ascending, diagonal last), U = the strict
+// upper part of L^T as scalar CSR, and 1 / l_uu.  Device pointers.
+constexpr int kBicMaxNodesPerBlock = 512;
+struct BicFactorDev {
+  int64_t n = 0;               // unknowns (3 nn)
+  int32_t rows_per_block = 0;  // 3 nodes_per_block
+  int32_t nblk = 0;
+  const int32_t* lrp = nullptr;  // [n + 1]
+  const int32_t* lcol = nullptr;
+  const double2* lval = nullptr;
+  const int32_t* urp = nullptr;  // [n + 1]
+  const int32_t* ucol = nullptr;
+  const double2* uval = nullptr;
+  const double2* ldinv = nullptr;  // [n]
+};
+
 // COCG scalar block of one right-hand side, kept on the device so the
 // host never waits inside an iteration.  Values that the iteration kernels
 // both read and write are kept in two slots indexed by the parity of the
@@ -282,6 +299,27 @@ hipError_t norm2_c128(hipStream_t st, int64_t n, const double2* v, double* parti
 
 int reduce_blocks_for(int64_t n);
 
+// Block incomplete Cholesky (bic_kernels.hip).  Pattern: per-row entry
+// counts of L, then columns and A's values at the scanned offsets; factor in
+// place (one thread per block; *bad = 1 on a zero or non-finite pivot),
+// writing ldinv; U from L (counts non-null: counts only, else fill at urp).
+hipError_t bic_pattern_count(hipStream_t st, const PatternDev& p, int32_t nodes_per_block, int32_t* counts);
+hipError_t bic_pattern_fill(hipStream_t st, const PatternDev& p, int32_t nodes_per_block, const double2* val,
+                            const int32_t* lrp, int32_t* lcol, double2* lval);
+hipError_t bic_factor(hipStream_t st, int64_t n, int32_t rows_per_block, int32_t nblk, const int32_t* lrp,
+                      const int32_t* lcol, double2* lval, double2* ldinv, int32_t* bad);
+hipError_t bic_upper(hipStream_t st, int64_t n, int32_t rows_per_block, const int32_t* lrp, const int32_t* lcol,
+                     const double2* lval, int32_t* counts, const int32_t* urp, int32_t* ucol, double2* uval);
+// z = (L L^T)^-1 r, one workgroup per block; r^T z (re, im), ||r||^2, ||z||^2
+// into out[0..3] (stage: 4 doubles per block; ticket: a zeroed counter the
+// launch leaves zeroed).  Skipped when sc (may be null) has stopped.
+hipError_t bic_apply(hipStream_t st, const BicFactorDev& f, const double2* r, double2* z, double* stage,
+                     uint32_t* ticket, double* out, const CocgScalars* sc);
+// Segment start from an application's totals: p = z, rho / ||r||^2 / start
+// verdict into slot par.
+hipError_t bic_init(hipStream_t st, int64_t n, const double2* z, double2* p, CocgScalars* sc, const double* sums,
+                    int par);
+
 }  // namespace k
 
 // ------------------------------------------------------------- host objects
@@ -331,6 +369,10 @@ struct Problem {
   double2* hval64 = nullptr;      // symmetric half store values (device, [stored][9])
   int64_t n_half = 0;             // stored blocks
   bool imported = false;          // built by femh_import_bsr: pattern and values only, no mesh
+  int32_t bic_nodes = 0;          // block incomplete Cholesky factor built for this block size (0: none)
+  int64_t bic_nnz_l = 0;
+  BicFactorDev bic{};
+  std::vector<void*> bic_mem;     // the factor's device memory (freed on a rebuild)
 
   std::vector<void*> owned;
   void* alloc(size_t bytes);  // tracked allocation, freed with the problem
@@ -350,6 +392,12 @@ int problem_create(Ctx* ctx, const femh_problem_desc* d, Problem** out);
 int problem_import(Ctx* ctx, int64_t nb, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
                    const femh_c128* vals, Problem** out);
 femh_solve_opts opts_with_defaults(const femh_solve_opts* o);
+// Options (after defaults) the solvers accept; batched: the columns of one
+// batched solve (no block incomplete Cholesky there).
+int check_solve_opts(const femh_solve_opts& o, bool batched, std::string& msg);
+// Extra device bytes of FEMH_PRECOND_BIC0: the factor and, per right-hand
+// side, the preconditioner's workspace.
+int64_t estimate_bic_bytes(const femh_problem_desc* d, int32_t nrhs);
 
 // Solve one right-hand side already assembled into b (device, FP64) into x
 // (device, FP64).  Fills one stats entry.  Workspace is allocated inside.
@@ -371,6 +419,10 @@ int autotune_spmm(Problem* P, const double2* val64, const double2* Pv, double2* 
 int ensure_row_order(Problem* P);
 // Builds the symmetric half store (P->hpos, P->hval64) once per problem.
 int ensure_half_store(Problem* P);
+// Builds the block incomplete Cholesky factor for blocks of nodes_per_block
+// nodes (kept until another block size is asked for).  FEMH_E_BREAKDOWN
+// when a pivot vanishes or is not finite (no factor is kept).
+int ensure_bic(Problem* P, int32_t nodes_per_block);
 
 // Single-RHS solve as a non-blocking state machine (one code path for
 // femh_solve and the server).  step() queues the work its phase allows and

@@ -2,6 +2,7 @@
 // footprint estimates and on-device numbering + assembly.
 #include <cmath>
 #include <cstdarg>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -55,6 +56,7 @@ Problem::~Problem() {
   if (ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (void* p : owned) ctx->dfree(p);
+    for (void* p : bic_mem) ctx->dfree(p);
   }
 }
 
@@ -242,6 +244,44 @@ int64_t estimate_bytes(const femh_problem_desc* d, int32_t nrhs, int32_t precisi
   return b;
 }
 
+int64_t estimate_bic_bytes(const femh_problem_desc* d, int32_t nrhs) {
+  int64_t nn, nnzb;
+  count_pattern(d, nn, nnzb);
+  // L and U hold at most 9 nnzb + 3 nn entries together (column + value),
+  // plus their row starts and 1 / l_uu; per right-hand side the
+  // preconditioned residual, a vector of ones and the reduction buffers
+  const int64_t factor = al(20 * (9 * nnzb + 3 * nn)) + 2 * al(12 * nn + 4) + al(48 * nn);
+  const int64_t per_rhs = 2 * al(48 * nn) + 2 * al(8 * 2048 * 4);
+  return factor + (int64_t)(nrhs > 0 ? nrhs : 0) * per_rhs;
+}
+
+int check_solve_opts(const femh_solve_opts& o, bool batched, std::string& msg) {
+  char buf[160];
+  if (o.precision != FEMH_FP64 && o.precision != FEMH_MIXED && o.precision != FEMH_MIXED_MATRIX) {
+    std::snprintf(buf, sizeof buf, "unknown precision %d", o.precision);
+    msg = buf;
+    return FEMH_E_INVALID;
+  }
+  if (o.precond != FEMH_PRECOND_JACOBI && o.precond != FEMH_PRECOND_NONE && o.precond != FEMH_PRECOND_BIC0) {
+    std::snprintf(buf, sizeof buf, "unknown preconditioner %d", o.precond);
+    msg = buf;
+    return FEMH_E_INVALID;
+  }
+  if (o.precond == FEMH_PRECOND_BIC0) {
+    if (batched || o.precision != FEMH_FP64) {
+      msg = "FEMH_PRECOND_BIC0 runs with single right-hand-side FEMH_FP64 solves only";
+      return FEMH_E_INVALID;
+    }
+    if (o.precond_block < 1 || o.precond_block > kBicMaxNodesPerBlock) {
+      std::snprintf(buf, sizeof buf, "precond_block must be 1..%d (got %d)", kBicMaxNodesPerBlock,
+                    o.precond_block);
+      msg = buf;
+      return FEMH_E_INVALID;
+    }
+  }
+  return FEMH_OK;
+}
+
 int64_t estimate_batch_workspace(const femh_problem_desc* d, int32_t nrhs) {
   int64_t nn, nnzb;
   count_pattern(d, nn, nnzb);
@@ -333,6 +373,91 @@ struct TmpBuf {
   }
   template <typename T> T* as() { return reinterpret_cast<T*>(p); }
 };
+
+// ------------------------------------------- block incomplete Cholesky
+static void drop_bic(Problem* P) {
+  if (!P->bic_mem.empty()) (void)hipStreamSynchronize(P->ctx->stream);
+  for (void* p : P->bic_mem) P->ctx->dfree(p);
+  P->bic_mem.clear();
+  P->bic = BicFactorDev{};
+  P->bic_nodes = 0;
+  P->bic_nnz_l = 0;
+}
+
+int ensure_bic(Problem* P, int32_t nodes_per_block) {
+  // checked first: bic_nodes is 0 while no factor is held
+  if (nodes_per_block < 1 || nodes_per_block > kBicMaxNodesPerBlock) {
+    set_error("block incomplete Cholesky: nodes per block must be 1..%d (got %d)", kBicMaxNodesPerBlock,
+              nodes_per_block);
+    return FEMH_E_INVALID;
+  }
+  if (P->bic_nodes == nodes_per_block) return FEMH_OK;
+  drop_bic(P);
+  Ctx* c = P->ctx;
+  hipStream_t s = c->stream;
+  const int64_t n = 3 * (int64_t)P->pat.nn;
+  const int32_t rpb = 3 * nodes_per_block;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = c->dmalloc(bytes > 0 ? bytes : 16);
+    if (p) P->bic_mem.push_back(p);
+    return p;
+  };
+  auto oom = [&]() {
+    drop_bic(P);
+    set_error("device allocation failed (block incomplete Cholesky factor)");
+    return FEMH_E_OOM;
+  };
+  TmpBuf counts(c, 4 * (size_t)n), tmp(c, 4 * (size_t)k::scan_tmp_ints(n)), flag(c, 64);
+  int32_t* lrp = (int32_t*)take(4 * ((size_t)n + 1));
+  int32_t* urp = (int32_t*)take(4 * ((size_t)n + 1));
+  double2* ldinv = (double2*)take(16 * (size_t)n);
+  if (!counts.p || !tmp.p || !flag.p || !lrp || !urp || !ldinv) return oom();
+  int32_t host[2] = {0, 0};
+  // L's pattern and A's values on it
+  FEMH_TRY_HIP(k::bic_pattern_count(s, P->pat, nodes_per_block, counts.as<int32_t>()));
+  FEMH_TRY_HIP(k::exclusive_scan(s, counts.as<int32_t>(), lrp, n, tmp.as<int32_t>(), lrp + n));
+  FEMH_TRY_HIP(hipMemcpyAsync(host, lrp + n, 4, hipMemcpyDeviceToHost, s));
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
+  const int64_t nnz_l = host[0];
+  int32_t* lcol = (int32_t*)take(4 * (size_t)nnz_l);
+  double2* lval = (double2*)take(16 * (size_t)nnz_l);
+  if (!lcol || !lval) return oom();
+  FEMH_TRY_HIP(k::bic_pattern_fill(s, P->pat, nodes_per_block, P->val64, lrp, lcol, lval));
+  // eq. (5) inside each block
+  const int32_t nblk = (int32_t)((n + rpb - 1) / rpb);
+  FEMH_TRY_HIP(hipMemsetAsync(flag.p, 0, 4, s));
+  FEMH_TRY_HIP(k::bic_factor(s, n, rpb, nblk, lrp, lcol, lval, ldinv, flag.as<int32_t>()));
+  FEMH_TRY_HIP(hipMemcpyAsync(host + 1, flag.p, 4, hipMemcpyDeviceToHost, s));
+  // U = strict upper part of L^T
+  FEMH_TRY_HIP(k::bic_upper(s, n, rpb, lrp, lcol, lval, counts.as<int32_t>(), nullptr, nullptr, nullptr));
+  FEMH_TRY_HIP(k::exclusive_scan(s, counts.as<int32_t>(), urp, n, tmp.as<int32_t>(), urp + n));
+  FEMH_TRY_HIP(hipMemcpyAsync(host, urp + n, 4, hipMemcpyDeviceToHost, s));
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
+  if (host[1]) {
+    drop_bic(P);
+    set_error("block incomplete Cholesky: a pivot vanished or is not finite");
+    return FEMH_E_BREAKDOWN;
+  }
+  const int64_t nnz_u = host[0];
+  int32_t* ucol = (int32_t*)take(4 * (size_t)nnz_u);
+  double2* uval = (double2*)take(16 * (size_t)nnz_u);
+  if (!ucol || !uval) return oom();
+  FEMH_TRY_HIP(k::bic_upper(s, n, rpb, lrp, lcol, lval, nullptr, urp, ucol, uval));
+  FEMH_TRY_HIP(hipStreamSynchronize(s));
+  P->bic.n = n;
+  P->bic.rows_per_block = rpb;
+  P->bic.nblk = nblk;
+  P->bic.lrp = lrp;
+  P->bic.lcol = lcol;
+  P->bic.lval = lval;
+  P->bic.urp = urp;
+  P->bic.ucol = ucol;
+  P->bic.uval = uval;
+  P->bic.ldinv = ldinv;
+  P->bic_nodes = nodes_per_block;
+  P->bic_nnz_l = nnz_l;
+  return FEMH_OK;
+}
 
 int problem_create(Ctx* ctx, const femh_problem_desc* d, Problem** out) {
   std::string msg;
@@ -547,6 +672,7 @@ femh_solve_opts opts_with_defaults(const femh_solve_opts* o) {
   // COCG-Jacobi's iteration count grows with the box size in wavelengths:
   // a 6.4-wavelength serving box (64^3) already needs 48 000 in FP64
   if (r.max_iter <= 0) r.max_iter = 200000;
+  if (r.precond_block == 0) r.precond_block = 64;
   // complex64 recurrences can only shrink their residual about one decade
   // before its rounding dominates; an FP64 recurrence with a complex64 matrix
   // can go much further between reliable updates

@@ -503,10 +503,19 @@ int femh_server_submit(femh_server* s, const femh_problem_desc* desc, int32_t nr
   r->waves.assign(waves, waves + nrhs);
   if (opts) r->opts = *opts;
   const femh_solve_opts o = femh::opts_with_defaults(opts);
+  const bool batched = s->batch_rhs && nrhs >= 2;
+  st = femh::check_solve_opts(o, batched, m);
+  if (st != FEMH_OK) {
+    delete r;
+    femh::set_error("%s", m.c_str());
+    return st;
+  }
   // problem + per-column solver workspace (+ the batched groups' blocks;
-  // batch_rhs is fixed when the server is created)
+  // batch_rhs is fixed when the server is created; + the block incomplete
+  // Cholesky factor and its workspace)
   int64_t base = femh::estimate_bytes(desc, nrhs, o.precision);
-  if (s->batch_rhs && nrhs >= 2) base += femh::estimate_batch_workspace(desc, nrhs);
+  if (batched) base += femh::estimate_batch_workspace(desc, nrhs);
+  if (o.precond == FEMH_PRECOND_BIC0) base += femh::estimate_bic_bytes(desc, nrhs);
   r->est_bytes = base;
   std::lock_guard<std::mutex> g(s->mu);
   ++s->submitted;

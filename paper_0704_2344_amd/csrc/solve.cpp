@@ -10,7 +10,9 @@
 // complex128 matrix, in its single-reduction form (one product and one
 // update kernel per iteration, see sr_update_c128); when the recursive
 // residual meets the tolerance the FP64 true residual b - A x is formed and,
-// if it does not meet it, COCG restarts from it.
+// if it does not meet it, COCG restarts from it.  With the block incomplete
+// Cholesky preconditioner (sections 3.1.5.2-3.1.5.3) the FP64 recurrence
+// runs in textbook order: product, update, z = M^-1 r, direction update.
 //
 // Matrix-mixed mode: the FP64 COCG recurrence with the complex64 matrix in
 // the product (values promoted, FP64 sums); reliable updates against the
@@ -71,16 +73,22 @@ struct Stepper {
   bool mixed = false;  // complex64 vectors and matrix
   bool m32 = false;    // complex64 matrix, complex128 vectors
   bool sr = false;     // FP64: single-reduction recurrence
+  bool bic = false;    // FP64 with block incomplete Cholesky (textbook order)
   int64_t n = 0;
   std::vector<void*> owned;
   // device workspace
   double2 *r64 = nullptr, *p64 = nullptr, *q64 = nullptr;
-  double2 *z64 = nullptr, *s64 = nullptr;  // single-reduction form: z = D^-1 r, s = A p (q64 holds A z)
+  double2 *z64 = nullptr, *s64 = nullptr;  // single-reduction form: z = D^-1 r, s = A p (q64 holds A z);
+                                           // block incomplete Cholesky: z = M^-1 r
   float2 *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
   void* partials = nullptr;  // SpMV -> update partials; also once-per-segment kernels
   void* partials_b = nullptr;  // update -> direction-update partials (single-reduction form:
                                // two buffers of 8 values per workgroup, update -> next
                                // update, by parity)
+  void* partials_c = nullptr;  // block incomplete Cholesky: the application's totals in slot 0,
+                               // the other slots zero (read as the direction update's partials)
+  double* bic_stage = nullptr;    // per-block sums of the application
+  uint32_t* bic_ticket = nullptr;  // its last-block counter
   CocgScalars* sc = nullptr;
   Aux* aux = nullptr;
   const double2* dinv64 = nullptr;
@@ -142,7 +150,8 @@ struct Stepper {
     o = opts;
     mixed = o.precision == FEMH_MIXED;
     m32 = o.precision == FEMH_MIXED_MATRIX;
-    sr = !mixed && !m32;
+    bic = !mixed && !m32 && o.precond == FEMH_PRECOND_BIC0;
+    sr = !mixed && !m32 && !bic;
     n = 3 * (int64_t)P->pat.nn;
     r64 = (double2*)dev(16 * n);
     if (!r64) return oom();
@@ -156,10 +165,13 @@ struct Stepper {
       p64 = (double2*)dev(16 * n);
       q64 = (double2*)dev(16 * n);
       if (!p64 || !q64) return oom();
-      if (sr) {
+      if (sr || bic) {
         z64 = (double2*)dev(16 * n);
+        if (!z64) return oom();
+      }
+      if (sr) {
         s64 = (double2*)dev(16 * n);
-        if (!z64 || !s64) return oom();
+        if (!s64) return oom();
       }
     }
     partials = dev(8 * kPartialSlots);
@@ -169,7 +181,17 @@ struct Stepper {
     if (!partials || !partials_b || !sc || !aux) return oom();
     dinv64 = P->dinv64;
     dinv32 = P->dinv32;
-    if (o.precond == FEMH_PRECOND_NONE) {
+    if (bic) {
+      // update and direction update run with D = I; z comes from the factor
+      FEMH_TRY(ensure_bic(P, o.precond_block));
+      partials_c = dev(8 * kPartialSlots);
+      bic_stage = (double*)dev(32 * (size_t)P->bic.nblk + 256);
+      if (!partials_c || !bic_stage) return oom();
+      bic_ticket = reinterpret_cast<uint32_t*>(bic_stage + 4 * (size_t)P->bic.nblk);
+      FEMH_TRY_HIP(hipMemsetAsync(partials_c, 0, 8 * kPartialSlots, s));
+      FEMH_TRY_HIP(hipMemsetAsync(bic_stage, 0, 32 * (size_t)P->bic.nblk + 256, s));
+    }
+    if (o.precond == FEMH_PRECOND_NONE || bic) {
       if (mixed) {
         float2* ones = (float2*)dev(8 * n);
         if (!ones) return oom();
@@ -208,6 +230,14 @@ struct Stepper {
     return FEMH_OK;
   }
 
+  // block incomplete Cholesky segment start from the residual in r64
+  int queue_bic_start() {
+    double* tot = reinterpret_cast<double*>(partials_c);
+    FEMH_TRY_HIP(k::bic_apply(s, P->bic, r64, z64, bic_stage, bic_ticket, tot, sc));
+    FEMH_TRY_HIP(k::bic_init(s, n, z64, p64, sc, tot, par()));
+    return FEMH_OK;
+  }
+
   // ---- queue helpers
   int queue_residual() {
     FEMH_TRY_HIP(k::residual_c128(s, P->pat, P->val64, x, b, r64, dpart(), aux->ticket, &aux->rr, P->spmv));
@@ -242,6 +272,15 @@ struct Stepper {
       if (prof) FEMH_TRY_HIP(hipEventRecord(e1, s));
       FEMH_TRY_HIP(k::sr_update_c128(s, n, dinv64, x, z64, q64, p64, s64, sc, partials, nin, bpart(pr),
                                      bpart(pr ^ 1), pr));
+    } else if (bic) {
+      // textbook order with z = M^-1 r between the update and the direction
+      // update, which reads the application's totals as its partials
+      FEMH_TRY_HIP(k::cocg_spmv_dot_c128(s, P->pat, P->val64, p64, q64, sc, partials, P->spmv));
+      if (prof) FEMH_TRY_HIP(hipEventRecord(e1, s));
+      FEMH_TRY_HIP(k::cocg_update_c128(s, n, dinv64, x, r64, p64, q64, sc, partials, nin, partials_b, pr));
+      FEMH_TRY_HIP(k::bic_apply(s, P->bic, r64, z64, bic_stage, bic_ticket,
+                                reinterpret_cast<double*>(partials_c), sc));
+      FEMH_TRY_HIP(k::cocg_pupdate_c128(s, n, dinv64, z64, p64, sc, partials_c, pr));
     } else {
       FEMH_TRY_HIP(k::cocg_spmv_dot_m32(s, P->pat, P->val32, p64, q64, sc, partials, P->spmv));
       if (prof) FEMH_TRY_HIP(hipEventRecord(e1, s));
@@ -316,6 +355,7 @@ struct Stepper {
       if (m32) hw->delta2 = o.inner_rtol * o.inner_rtol;
       FEMH_TRY_HIP(hipMemcpyAsync(sc, hw, sizeof(*hw), hipMemcpyHostToDevice, s));
       if (sr) FEMH_TRY(queue_sr_init());
+      else if (bic) FEMH_TRY(queue_bic_start());
       else FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, partials, 0, par()));
     }
     new_segment(0);
@@ -364,6 +404,7 @@ struct Stepper {
       if (m32) hw->delta2 = o.inner_rtol * o.inner_rtol;
       FEMH_TRY_HIP(hipMemcpyAsync(sc, hw, sizeof(*hw), hipMemcpyHostToDevice, s));
       if (sr) FEMH_TRY(queue_sr_init());
+      else if (bic) FEMH_TRY(queue_bic_start());
       else FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, partials, 0, par()));
     }
     new_segment(iters);

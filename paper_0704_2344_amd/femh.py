@@ -42,6 +42,7 @@ FEMH_MIXED = 1
 FEMH_MIXED_MATRIX = 2
 FEMH_PRECOND_JACOBI = 0
 FEMH_PRECOND_NONE = 1
+FEMH_PRECOND_BIC0 = 2
 
 
 class FemhError(RuntimeError):
@@ -76,7 +77,8 @@ class femh_plane_wave(C.Structure):
 
 class femh_solve_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("rtol", C.c_double),
-                ("max_iter", C.c_int32), ("inner_rtol", C.c_double), ("max_outer", C.c_int32),
+                ("max_iter", C.c_int32), ("precond_block", C.c_int32), ("inner_rtol", C.c_double),
+                ("max_outer", C.c_int32),
                 ("check_every", C.c_int32)]
 
 
@@ -141,6 +143,7 @@ SIGNATURES = {
     "femh_export_bsr_c64": (C.c_int, [P, P]),
     "femh_export_rhs": (C.c_int, [P, I32, C.POINTER(femh_plane_wave), P]),
     "femh_export_jacobi": (C.c_int, [P, P]),
+    "femh_export_bic0": (C.c_int, [P, I32, C.POINTER(I64), P, P, P]),
     "femh_spmv_dev": (C.c_int, [P, I32, P, P, I32, PD]),
     "femh_spmm_dev": (C.c_int, [P, I32, I32, P, P, I32, PD]),
     "femh_spmm_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
@@ -285,10 +288,11 @@ def make_waves(waves: Sequence) -> "C.Array":
 
 
 def make_opts(precision=FEMH_FP64, rtol=1e-6, max_iter=0, inner_rtol=0.0, max_outer=0,
-              check_every=0, precond=FEMH_PRECOND_JACOBI) -> femh_solve_opts:
+              check_every=0, precond=FEMH_PRECOND_JACOBI, precond_block=0) -> femh_solve_opts:
     o = femh_solve_opts()
     o.precision = precision
     o.precond = precond
+    o.precond_block = precond_block
     o.rtol = rtol
     o.max_iter = max_iter
     o.inner_rtol = inner_rtol
@@ -539,6 +543,19 @@ class Problem:
         d = np.zeros(self.n_unknowns, dtype=np.complex128)
         check(self.lib.femh_export_jacobi(self.handle, d.ctypes.data))
         return d
+
+    def export_bic0(self, nodes_per_block=64):
+        """The block incomplete Cholesky factor L (scalar CSR: row_ptr, col,
+        vals; columns ascending, diagonal last) for blocks of nodes_per_block
+        nodes, built on the device if needed."""
+        nnz = I64(0)
+        check(self.lib.femh_export_bic0(self.handle, nodes_per_block, C.byref(nnz), None, None, None))
+        row_ptr = np.zeros(self.n_unknowns + 1, dtype=np.int32)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        vals = np.zeros(nnz.value, dtype=np.complex128)
+        check(self.lib.femh_export_bic0(self.handle, nodes_per_block, C.byref(nnz), row_ptr.ctypes.data,
+                                        col.ctypes.data, vals.ctypes.data))
+        return row_ptr, col, vals
 
     def spmv_dev(self, x, y, precision=FEMH_FP64, reps=1):
         dt = _vector_dtype(precision)
