@@ -282,6 +282,63 @@ def spmv_event_roofline(ctx_slot_sec, ctx_slot_cnt, nn, nnzb, val_bytes, vec_byt
             "note": note}
 
 
+def bic_apply_bytes(n, nnz_l, rows_per_block):
+    """Algorithmic bytes of one block incomplete Cholesky application: the
+    factor once per sweep (L with its diagonal, U without: 16-byte value and
+    4-byte column per entry, 4-byte row starts), 1 / l_uu once per sweep, r
+    read twice (the start and the closing dot products), z written once."""
+    nnz_u = nnz_l - n
+    nblk = -(-n // rows_per_block)
+    return 20 * (nnz_l + nnz_u) + 8 * (n + 1) + 2 * 16 * n + 3 * 16 * n + 64 * nblk
+
+
+def bicp_leg(ctx, F, W, torch, dev, with_sphere, blocks=(4, 16, 64)):
+    """FP64 COCG with Jacobi against block incomplete Cholesky (blocks of B
+    nodes) on the 30^3 PEC cube to 1e-8 (and the 60^3 coated sphere to 1e-6
+    when asked): iterations, solve time, time per iteration, and the
+    application alone (femh_bic0_apply_dev, HIP events).  Each solve runs
+    twice; the first includes building the factor."""
+    cases = [("pec_cube_30", W.pec_cube(30), 1e-8,
+              "30^3 hexahedra, centred PEC cube of one wavelength, ABC outer faces, one seeded wave")]
+    if with_sphere:
+        cases.append(("pec_sphere_shell_60", W.pec_sphere_shell(60), 1e-6,
+                      "60^3 hexahedra, PEC sphere with a lossy dielectric shell, one seeded wave"))
+    out = {}
+    for name, (prob, waves), rtol, what in cases:
+        P = F.Problem(ctx, prob)
+        o = torch.zeros(P.grid_shape(1), dtype=torch.complex128, device=dev)
+        leg = {"workload": f"{name}: {what}; FP64 COCG to {rtol:g}; {P.n_unknowns} unknowns, {P.nnzb} blocks"}
+        rv = torch.randn(P.n_unknowns, dtype=torch.complex128, device=dev)
+        zv = torch.zeros_like(rv)
+        runs = [("jacobi", {})] + [(f"bic0_{b}", dict(precond=F.FEMH_PRECOND_BIC0, precond_block=b)) for b in blocks]
+        for tag, kw in runs:
+            times = []
+            for _ in range(2):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                st, stc = P.solve_dev(waves, o, precision=F.FEMH_FP64, rtol=rtol, **kw)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - a)
+            s0 = st[0]
+            r = {"status": stc, "iters": s0["iters"], "restarts": s0["outer_iters"], "rel_residual": s0["rel_residual"],
+                 "solve_s": times[1], "us_per_iter": times[1] / max(s0["iters"], 1) * 1e6,
+                 "first_solve_s": times[0]}
+            if tag != "jacobi":
+                nodes = kw["precond_block"]
+                _, col, _ = P.export_bic0(nodes)
+                t_apply = P.bic0_apply_dev(rv, zv, nodes, reps=20)
+                nbytes = bic_apply_bytes(P.n_unknowns, len(col), 3 * nodes)
+                r.update({"factor_entries": len(col), "apply_us": t_apply * 1e6, "apply_bytes": nbytes,
+                          "apply_GBps": nbytes / t_apply / 1e9,
+                          "time_vs_jacobi": times[1] / leg["jacobi"]["solve_s"]})
+            leg[tag] = r
+            log(f"  bicp {name} {tag}: {s0['iters']} iterations, {times[1]:.3f} s"
+                + (f", apply {r['apply_us']:.1f} us" if "apply_us" in r else ""))
+        out[name] = leg
+        P.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,8 +348,10 @@ def main():
                     help="timed FP64 steps beside the headline (0 skips FP64 and the complex64-vector solve)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip every leg but the headline")
-    ap.add_argument("--extras", default="cube,hbm,batched,planes,serving",
-                    help="legs after the headline, comma-separated subset of cube,hbm,batched,planes,serving")
+    ap.add_argument("--extras", default="cube,hbm,batched,planes,bicp,serving",
+                    help="legs after the headline, comma-separated subset of cube,hbm,batched,planes,bicp,serving")
+    ap.add_argument("--bicp-sphere", action="store_true",
+                    help="bicp leg: also the 60^3 coated sphere (about a minute of solves)")
     ap.add_argument("--cube-steps", type=int, default=10)
     ap.add_argument("--batched-singles", type=int, default=2,
                     help="single-RHS solves per precision timed beside the batched leg (0 skips them)")
@@ -427,7 +486,7 @@ def main():
         result["copy_probe_GBps"] = ctx.bw_probe(1 << 30, 3)
 
     legs = set() if args.no_extras else {x for x in args.extras.split(",") if x}
-    unknown = legs - {"cube", "hbm", "batched", "planes", "serving"}
+    unknown = legs - {"cube", "hbm", "batched", "planes", "bicp", "serving"}
     if unknown:
         raise SystemExit(f"unknown --extras legs: {sorted(unknown)}")
 
@@ -559,6 +618,10 @@ def main():
                                 "wave along +z, FP64 to 1e-8; the quarter x >= 0, y >= 0 with n x H = 0 on x = 0 "
                                 "and n . H = 0 on y = 0")
         result["planes"] = legs_out
+
+    if "bicp" in legs:
+        log("leg bicp")
+        result["bicp"] = bicp_leg(ctx, F, W, torch, dev, args.bicp_sphere)
 
     if "serving" in legs:
         log("leg serving")

@@ -136,7 +136,7 @@ typedef struct {
   int32_t precond;       /* femh_precond; default Jacobi */
   double rtol;           /* stop at ||b - A x||_2 <= rtol ||b||_2 (FP64 true residual); default 1e-6 */
   int32_t max_iter;      /* Krylov iterations in total (inner ones for MIXED); default 200000 */
-  int32_t precond_block; /* FEMH_PRECOND_BIC0: nodes per block, 1..512; default 64 (ignored otherwise) */
+  int32_t precond_block; /* FEMH_PRECOND_BIC0: nodes per block, 1..512; default 16 (ignored otherwise) */
   double inner_rtol;     /* MIXED*: residual reduction between reliable updates; default 0.1
                             (FEMH_MIXED), 1e-3 (FEMH_MIXED_MATRIX) */
   int32_t max_outer;     /* MIXED: refinement steps; default 20 */
@@ -296,6 +296,16 @@ int femh_export_jacobi(const femh_problem* prob, femh_c128* dinv);
  * FEMH_E_BREAKDOWN (a pivot vanished or is not finite), FEMH_E_OOM. */
 int femh_export_bic0(femh_problem* prob, int32_t nodes_per_block, int64_t* nnz, int32_t* row_ptr, int32_t* col_idx,
                      femh_c128* vals);
+
+/* z = (L L^T)^-1 r with the FEMH_PRECOND_BIC0 factor for blocks of
+ * nodes_per_block nodes (eq. (6)'s forward and back substitution inside
+ * each block), the factor built if the problem does not hold it yet.  r_dev
+ * and z_dev are device arrays [n_unknowns] complex128 (distinct).  The
+ * application runs `reps` >= 1 times; *avg_seconds (may be NULL) receives
+ * the mean kernel time measured with HIP events on the context's stream.
+ * Errors as femh_export_bic0. */
+int femh_bic0_apply_dev(femh_problem* prob, int32_t nodes_per_block, const femh_c128* r_dev, femh_c128* z_dev,
+                        int32_t reps, double* avg_seconds);
 
 /* y = A x on device vectors of n_unknowns complex entries: complex128 for
  * FEMH_FP64, complex64 with FP32 accumulation for FEMH_MIXED, the complex64

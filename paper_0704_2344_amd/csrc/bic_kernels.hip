@@ -22,15 +22,15 @@
 // one lane per entry (distinct v, so no reduction and no conflict).  Back
 // (L^T z = y): for u descending, z_u = y_u / l_uu, then y_v -= l_uv z_u over
 // row u of L.  The rows' entries are staged into LDS in chunks of up to 64
-// rows, so each step reads only LDS.
+// rows, so each step reads only LDS, and a step needs no barrier (one
+// wavefront, whose LDS operations complete in order).
 #include "internal.h"
 
 namespace femh {
 namespace {
 
 constexpr int kFactorThreads = 64;
-constexpr int kChunkCap = 3 * kBicMaxNodesPerBlock;  // staged entries per chunk (>= the longest row)
-constexpr int kChunkRows = 64;                       // staged rows per chunk (one per lane)
+constexpr int kChunkRows = 64;  // staged rows per chunk (one per lane)
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -183,19 +183,17 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Rows [c0, c0 + cnt) of the CSR rows (rp, col, val) staged in LDS, with
-// their 1 / l_uu; a chunk takes up to kChunkRows rows and kChunkCap entries.
-// One row always fits, so every chunk advances: a row of L has at most 27
-// blocks (81 entries), a row of U at most the block's later rows
-// (3 * 512 - 1 = 1535).  Columns become block-relative.
+// A chunk of staged rows in LDS (layout from the launch's dynamic LDS): up
+// to kChunkRows rows and cap entries, where cap is at least the factor's
+// longest row, so every chunk advances.  Columns are block-relative.
 struct Chunk {
-  double2 val[kChunkCap];
-  int32_t col[kChunkCap];
-  int32_t rp[kChunkRows + 1];
-  double2 dinv[kChunkRows];
+  double2* val;   // [cap]
+  double2* dinv;  // [kChunkRows] 1 / l_uu of the chunk's rows
+  int32_t* col;   // [cap]
+  int32_t* rp;    // [kChunkRows + 1] row starts relative to the chunk
 };
 
-__device__ __forceinline__ void stage_rows(Chunk& ch, int64_t u0, int32_t c0, int32_t cnt,
+__device__ __forceinline__ void stage_rows(const Chunk& ch, int64_t u0, int32_t c0, int32_t cnt,
                                            const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                            const double2* __restrict__ val, const double2* __restrict__ dinv,
                                            int lane) {
@@ -210,72 +208,125 @@ __device__ __forceinline__ void stage_rows(Chunk& ch, int64_t u0, int32_t c0, in
   }
 }
 
-// z = (L L^T)^-1 r for block blockIdx.x (dynamic LDS: the block's slice of
-// the vector, rows_per_block complex); the block's r^T z (re, im), ||r||^2
-// and ||z||^2 go to stage[block][4], and the last workgroup to finish sums
-// them in block order into out[0..3] (the other slots of out are not
-// touched).  Returns at once when the recurrence has stopped (no workgroup
-// of this launch writes the flag).
-__global__ void __launch_bounds__(64) k_bic_apply(int64_t n, int32_t rows_per_block, const int32_t* __restrict__ lrp,
-                                                  const int32_t* __restrict__ lcol, const double2* __restrict__ lval,
-                                                  const int32_t* __restrict__ urp, const int32_t* __restrict__ ucol,
-                                                  const double2* __restrict__ uval, const double2* __restrict__ ldinv,
-                                                  const double2* __restrict__ r, double2* __restrict__ z,
-                                                  double* __restrict__ stage, uint32_t* ticket,
-                                                  double* __restrict__ out, const CocgScalars* sc) {
+// The column steps of one staged chunk, ascending (forward sweep, U rows) or
+// descending (back sweep, L rows without their diagonal).  Step k: y_k *=
+// 1 / l_kk, then y_v -= w y_k over the row's entries (v, w), one lane per
+// entry; a lane without an entry updates the spare slot y[spare] with
+// weight 0, so every lane issues the same two reads and one write, with no
+// branch, and the two reads are in flight together.  kLong: some row of
+// the chunk has more than 64 entries, and lanes loop over the rest.  Lane t
+// keeps row t's bounds in registers, read back per step with readlane; each
+// lane's entry of the next row is read from LDS a step ahead (at a clamped
+// index, then selected).  One wavefront owns the block and its LDS
+// operations complete in issue order, so a step sees every earlier step's
+// updates without a barrier.
+template <bool kBack, bool kLong>
+__device__ __forceinline__ void sweep_chunk(double2* y, int32_t spare, const Chunk& ch, int32_t cap, int32_t c0,
+                                            int32_t cnt, int lane) {
+  const int32_t my_s = lane < cnt ? ch.rp[lane] : 0;
+  const int32_t my_e = lane < cnt ? ch.rp[lane + 1] - (kBack ? 1 : 0) : 0;
+  int32_t k = kBack ? cnt - 1 : 0;
+  int32_t rs = __builtin_amdgcn_readlane(my_s, k), re = __builtin_amdgcn_readlane(my_e, k);
+  auto fetch = [&](int32_t& v, double2& w) {
+    const int32_t i = min(rs + lane, cap - 1);
+    const bool has = rs + lane < re;
+    const int32_t c = ch.col[i];
+    const double2 x = ch.val[i];
+    v = has ? c : spare;
+    w = has ? x : make_double2(0.0, 0.0);
+  };
+  int32_t v;
+  double2 w;
+  fetch(v, w);
+  double2 d = ch.dinv[k];
+  for (int32_t step = 0; step < cnt; ++step) {
+    const double2 yc = y[c0 + k];
+    double2 yv = y[v];
+    const double2 yk = cmul(yc, d);
+    const double2 t = cmul(w, yk);
+    yv.x -= t.x;
+    yv.y -= t.y;
+    y[v] = yv;
+    if (kLong) {
+      for (int32_t x = rs + 64 + lane; x < re; x += 64) {
+        const int32_t vx = ch.col[x];
+        const double2 tx = cmul(ch.val[x], yk);
+        double2 yx = y[vx];
+        yx.x -= tx.x;
+        yx.y -= tx.y;
+        y[vx] = yx;
+      }
+    }
+    y[c0 + k] = yk;  // every lane stores the same value
+    if (step + 1 < cnt) {
+      k += kBack ? -1 : 1;
+      rs = __builtin_amdgcn_readlane(my_s, k);
+      re = __builtin_amdgcn_readlane(my_e, k);
+      fetch(v, w);
+      d = ch.dinv[k];
+    }
+  }
+}
+
+template <bool kBack>
+__device__ __forceinline__ void sweep(double2* y, int32_t spare, const Chunk& ch, int32_t cap, int32_t c0,
+                                      int32_t cnt, int lane) {
+  const int32_t len = lane < cnt ? ch.rp[lane + 1] - ch.rp[lane] : 0;
+  if (__ballot(len > 64)) sweep_chunk<kBack, true>(y, spare, ch, cap, c0, cnt, lane);
+  else sweep_chunk<kBack, false>(y, spare, ch, cap, c0, cnt, lane);
+}
+
+// z = (L L^T)^-1 r for block blockIdx.x.  Dynamic LDS (bic_apply_lds): the
+// block's slice of the vector (rows_per_block complex) and a spare slot,
+// then one chunk of cap entries.  The block's r^T z (re, im), ||r||^2 and
+// ||z||^2 go to stage[block][4] (k_bic_sum adds them up).  Returns at once
+// when the recurrence has stopped (no workgroup of this launch writes the
+// flag).
+__global__ void __launch_bounds__(64) k_bic_apply(int64_t n, int32_t rows_per_block, int32_t cap,
+                                                  const int32_t* __restrict__ lrp, const int32_t* __restrict__ lcol,
+                                                  const double2* __restrict__ lval, const int32_t* __restrict__ urp,
+                                                  const int32_t* __restrict__ ucol, const double2* __restrict__ uval,
+                                                  const double2* __restrict__ ldinv, const double2* __restrict__ r,
+                                                  double2* __restrict__ z, double* __restrict__ stage,
+                                                  const CocgScalars* sc) {
   if (sc && __builtin_amdgcn_readfirstlane(sc->done)) return;
-  extern __shared__ double2 y[];
-  __shared__ Chunk ch;
-  __shared__ int s_last;
+  extern __shared__ double2 lds[];
+  double2* y = lds;
+  Chunk ch;
+  ch.val = lds + rows_per_block + 1;
+  ch.dinv = ch.val + cap;
+  ch.col = reinterpret_cast<int32_t*>(ch.dinv + kChunkRows);
+  ch.rp = ch.col + cap;
   const int lane = threadIdx.x;
   const int64_t u0 = (int64_t)blockIdx.x * rows_per_block;
   const int32_t m = (int32_t)(u0 + rows_per_block < n ? rows_per_block : n - u0);
   for (int32_t t = lane; t < m; t += 64) y[t] = r[u0 + t];
+  if (lane == 0) y[rows_per_block] = make_double2(0.0, 0.0);
+  __syncthreads();
   // forward sweep over the columns of L (rows of U), ascending
   for (int32_t c0 = 0; c0 < m;) {
     const int32_t base = urp[u0 + c0];
-    const bool fits = c0 + lane + 1 <= m && urp[u0 + c0 + lane + 1] - base <= kChunkCap;
+    const bool fits = c0 + lane + 1 <= m && urp[u0 + c0 + lane + 1] - base <= cap;
     const int32_t cnt = (int32_t)__popcll(__ballot(fits));
     __syncthreads();
     stage_rows(ch, u0, c0, cnt, urp, ucol, uval, ldinv, lane);
     __syncthreads();
-    for (int32_t k = 0; k < cnt; ++k) {
-      const double2 yu = cmul(y[c0 + k], ch.dinv[k]);
-      const int32_t e1 = ch.rp[k + 1];
-      for (int32_t e = ch.rp[k] + lane; e < e1; e += 64) {
-        const int32_t v = ch.col[e];
-        const double2 t = cmul(ch.val[e], yu);
-        y[v].x -= t.x;
-        y[v].y -= t.y;
-      }
-      if (lane == 0) y[c0 + k] = yu;
-      __syncthreads();
-    }
+    sweep<false>(y, rows_per_block, ch, cap, c0, cnt, lane);
     c0 += cnt;
   }
   // back sweep over the rows of L (diagonal last, not used), descending
   for (int32_t c1 = m; c1 > 0;) {
     const int32_t top = lrp[u0 + c1];
-    const bool fits = c1 - 1 - lane >= 0 && top - lrp[u0 + c1 - 1 - lane] <= kChunkCap;
+    const bool fits = c1 - 1 - lane >= 0 && top - lrp[u0 + c1 - 1 - lane] <= cap;
     const int32_t cnt = (int32_t)__popcll(__ballot(fits));
     const int32_t c0 = c1 - cnt;
     __syncthreads();
     stage_rows(ch, u0, c0, cnt, lrp, lcol, lval, ldinv, lane);
     __syncthreads();
-    for (int32_t k = cnt - 1; k >= 0; --k) {
-      const double2 zu = cmul(y[c0 + k], ch.dinv[k]);
-      const int32_t e1 = ch.rp[k + 1] - 1;
-      for (int32_t e = ch.rp[k] + lane; e < e1; e += 64) {
-        const int32_t v = ch.col[e];
-        const double2 t = cmul(ch.val[e], zu);
-        y[v].x -= t.x;
-        y[v].y -= t.y;
-      }
-      if (lane == 0) y[c0 + k] = zu;
-      __syncthreads();
-    }
+    sweep<true>(y, rows_per_block, ch, cap, c0, cnt, lane);
     c1 = c0;
   }
+  __syncthreads();
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int32_t t = lane; t < m; t += 64) {
     const double2 zt = y[t], rt = r[u0 + t];
@@ -289,26 +340,55 @@ __global__ void __launch_bounds__(64) k_bic_apply(int64_t n, int32_t rows_per_bl
   for (int k = 0; k < 4; ++k) acc[k] = wave_sum(acc[k]);
   if (lane == 0) {
 #pragma unroll
+    for (int k = 0; k < 4; ++k) stage[(size_t)blockIdx.x * 4 + k] = acc[k];
+  }
+}
+
+// The application's per-block sums, added in a fixed order: workgroup g
+// sums blocks [g per, (g + 1) per) (thread t every 256th, then a tree), and
+// the last workgroup to finish adds the workgroup totals in order into
+// out[0..3].  gsum: 4 doubles per workgroup; ticket: zero, and left zero.
+constexpr int kSumThreads = 256;
+constexpr int kSumGroups = 64;
+__global__ void __launch_bounds__(kSumThreads) k_bic_sum(int32_t nblk, int32_t per, const double* __restrict__ stage,
+                                                         double* gsum, uint32_t* ticket, double* __restrict__ out,
+                                                         const CocgScalars* sc) {
+  if (sc && __builtin_amdgcn_readfirstlane(sc->done)) return;
+  __shared__ double s[4][kSumThreads];
+  __shared__ int s_last;
+  const int32_t b0 = blockIdx.x * per;
+  const int32_t b1 = b0 + per < nblk ? b0 + per : nblk;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t b = b0 + threadIdx.x; b < b1; b += kSumThreads)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] += stage[(size_t)b * 4 + k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s[k][threadIdx.x] = t[k];
+  __syncthreads();
+  for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
     for (int k = 0; k < 4; ++k)
-      __hip_atomic_store(&stage[(size_t)blockIdx.x * 4 + k], acc[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&gsum[(size_t)blockIdx.x * 4 + k], s[k][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __threadfence();
     s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
   }
   __syncthreads();
-  if (!s_last) return;
+  if (!s_last || threadIdx.x != 0) return;
   __threadfence();
   double tot[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int32_t b = lane; b < (int32_t)gridDim.x; b += 64)
+  for (int32_t g = 0; g < (int32_t)gridDim.x; ++g)
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      tot[k] += __hip_atomic_load(&stage[(size_t)b * 4 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      tot[k] += __hip_atomic_load(&gsum[(size_t)g * 4 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) tot[k] = wave_sum(tot[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) out[k] = tot[k];
-    *ticket = 0u;  // ready for the next launch (the kernel boundary orders it)
-  }
+  for (int k = 0; k < 4; ++k) out[k] = tot[k];
+  *ticket = 0u;  // ready for the next launch (the kernel boundary orders it)
 }
 
 // Segment start after an application z = M^-1 r whose totals are in
@@ -371,12 +451,27 @@ hipError_t bic_upper(hipStream_t st, int64_t n, int32_t rows_per_block, const in
   return hipGetLastError();
 }
 
+size_t bic_apply_lds(int32_t rows_per_block, int32_t cap) {
+  return sizeof(double2) * ((size_t)rows_per_block + 1 + (size_t)cap + kChunkRows) +
+         sizeof(int32_t) * ((size_t)cap + kChunkRows + 1);
+}
+
+size_t bic_stage_doubles(int32_t nblk) { return 4 * (size_t)nblk + 4 * (size_t)kSumGroups; }
+
 hipError_t bic_apply(hipStream_t st, const BicFactorDev& f, const double2* r, double2* z, double* stage,
                      uint32_t* ticket, double* out, const CocgScalars* sc) {
   if (f.nblk == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bic_apply, dim3((unsigned)f.nblk), dim3(64), sizeof(double2) * (size_t)f.rows_per_block, st,
-                     f.n, f.rows_per_block, f.lrp, f.lcol,
-                     f.lval, f.urp, f.ucol, f.uval, f.ldinv, r, z, stage, ticket, out, sc);
+  hipLaunchKernelGGL(k_bic_apply, dim3((unsigned)f.nblk), dim3(64), bic_apply_lds(f.rows_per_block, f.chunk_cap),
+                     st, f.n, f.rows_per_block, f.chunk_cap, f.lrp, f.lcol, f.lval, f.urp, f.ucol, f.uval, f.ldinv, r,
+                     z, stage, sc);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // at least 256 blocks per summing workgroup, at most kSumGroups workgroups
+  int32_t groups = (f.nblk + kSumThreads - 1) / kSumThreads;
+  if (groups > kSumGroups) groups = kSumGroups;
+  const int32_t per = (f.nblk + groups - 1) / groups;
+  hipLaunchKernelGGL(k_bic_sum, dim3((unsigned)groups), dim3(kSumThreads), 0, st, f.nblk, per, stage,
+                     stage + 4 * (size_t)f.nblk, ticket, out, sc);
   return hipGetLastError();
 }
 

@@ -550,6 +550,42 @@ int femh_export_bic0(femh_problem* p, int32_t nodes_per_block, int64_t* nnz, int
   return FEMH_OK;
 }
 
+int femh_bic0_apply_dev(femh_problem* p, int32_t nodes_per_block, const femh_c128* r, femh_c128* z, int32_t reps,
+                        double* avg_seconds) {
+  femh::clear_error();
+  if (!p || !r || !z || reps < 1 || (const void*)r == (const void*)z) {
+    femh::set_error("prob, r and z must not be NULL, r and z distinct; reps >= 1");
+    return FEMH_E_INVALID;
+  }
+  Ctx* c = p->ctx;
+  FEMH_TRY_HIP(hipSetDevice(c->device));
+  FEMH_TRY(femh::ensure_bic(p, nodes_per_block));
+  const size_t stage_bytes = 8 * femh::k::bic_stage_doubles(p->bic.nblk) + 256;
+  DevTmp stage(c, stage_bytes), out(c, 64);
+  if (!stage.p || !out.p) {
+    femh::set_error("device allocation failed (application sums)");
+    return FEMH_E_OOM;
+  }
+  double* st = (double*)stage.p;
+  uint32_t* ticket = reinterpret_cast<uint32_t*>(st + femh::k::bic_stage_doubles(p->bic.nblk));
+  FEMH_TRY_HIP(hipMemsetAsync(stage.p, 0, stage_bytes, c->stream));
+  hipEvent_t e0, e1;
+  FEMH_TRY_HIP(hipEventCreate(&e0));
+  FEMH_TRY_HIP(hipEventCreate(&e1));
+  FEMH_TRY_HIP(hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i)
+    FEMH_TRY_HIP(femh::k::bic_apply(c->stream, p->bic, (const double2*)r, (double2*)z, st, ticket, (double*)out.p,
+                                    nullptr));
+  FEMH_TRY_HIP(hipEventRecord(e1, c->stream));
+  FEMH_TRY_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (avg_seconds) *avg_seconds = ms * 1e-3 / reps;
+  return FEMH_OK;
+}
+
 int femh_spmv_dev(femh_problem* p, int32_t precision, const void* x, void* y, int32_t reps, double* avg_seconds) {
   femh::clear_error();
   if (!p || !x || !y || reps < 1 ||

@@ -71,6 +71,7 @@ struct BicFactorDev {
   int64_t n = 0;               // unknowns (3 nn)
   int32_t rows_per_block = 0;  // 3 nodes_per_block
   int32_t nblk = 0;
+  int32_t chunk_cap = 0;       // entries the application stages at a time (>= the longest row of L and U)
   const int32_t* lrp = nullptr;  // [n + 1]
   const int32_t* lcol = nullptr;
   const double2* lval = nullptr;
@@ -310,9 +311,11 @@ hipError_t bic_factor(hipStream_t st, int64_t n, int32_t rows_per_block, int32_t
                       const int32_t* lcol, double2* lval, double2* ldinv, int32_t* bad);
 hipError_t bic_upper(hipStream_t st, int64_t n, int32_t rows_per_block, const int32_t* lrp, const int32_t* lcol,
                      const double2* lval, int32_t* counts, const int32_t* urp, int32_t* ucol, double2* uval);
-// z = (L L^T)^-1 r, one workgroup per block; r^T z (re, im), ||r||^2, ||z||^2
-// into out[0..3] (stage: 4 doubles per block; ticket: a zeroed counter the
-// launch leaves zeroed).  Skipped when sc (may be null) has stopped.
+// z = (L L^T)^-1 r, one workgroup per block, then r^T z (re, im), ||r||^2,
+// ||z||^2 summed in a fixed order into out[0..3] (stage: bic_stage_doubles
+// doubles; ticket: a zeroed counter the launches leave zeroed).  Skipped
+// when sc (may be null) has stopped.
+size_t bic_stage_doubles(int32_t nblk);
 hipError_t bic_apply(hipStream_t st, const BicFactorDev& f, const double2* r, double2* z, double* stage,
                      uint32_t* ticket, double* out, const CocgScalars* sc);
 // Segment start from an application's totals: p = z, rho / ||r||^2 / start

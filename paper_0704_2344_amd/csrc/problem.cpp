@@ -1,5 +1,6 @@
 // Host side of problem set-up: errors, contexts, descriptor validation,
 // footprint estimates and on-device numbering + assembly.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -249,9 +250,11 @@ int64_t estimate_bic_bytes(const femh_problem_desc* d, int32_t nrhs) {
   count_pattern(d, nn, nnzb);
   // L and U hold at most 9 nnzb + 3 nn entries together (column + value),
   // plus their row starts and 1 / l_uu; per right-hand side the
-  // preconditioned residual, a vector of ones and the reduction buffers
+  // preconditioned residual, a vector of ones, the direction update's
+  // partial sums and the application's per-block sums (at most one block
+  // per node)
   const int64_t factor = al(20 * (9 * nnzb + 3 * nn)) + 2 * al(12 * nn + 4) + al(48 * nn);
-  const int64_t per_rhs = 2 * al(48 * nn) + 2 * al(8 * 2048 * 4);
+  const int64_t per_rhs = 2 * al(48 * nn) + al(8 * 2048 * 4) + al(32 * nn + 8 * 256 + 256);
   return factor + (int64_t)(nrhs > 0 ? nrhs : 0) * per_rhs;
 }
 
@@ -443,7 +446,15 @@ int ensure_bic(Problem* P, int32_t nodes_per_block) {
   double2* uval = (double2*)take(16 * (size_t)nnz_u);
   if (!ucol || !uval) return oom();
   FEMH_TRY_HIP(k::bic_upper(s, n, rpb, lrp, lcol, lval, nullptr, urp, ucol, uval));
+  // the application stages rows in chunks of at least the longest row; 768
+  // entries (about 64 rows of a 64-node block) keep its LDS near 20 KB
+  std::vector<int32_t> hl((size_t)n + 1), hu((size_t)n + 1);
+  FEMH_TRY_HIP(hipMemcpyAsync(hl.data(), lrp, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+  FEMH_TRY_HIP(hipMemcpyAsync(hu.data(), urp, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
   FEMH_TRY_HIP(hipStreamSynchronize(s));
+  int32_t longest = 0;
+  for (int64_t u = 0; u < n; ++u) longest = std::max(longest, std::max(hl[u + 1] - hl[u], hu[u + 1] - hu[u]));
+  P->bic.chunk_cap = std::max(longest, 768);
   P->bic.n = n;
   P->bic.rows_per_block = rpb;
   P->bic.nblk = nblk;
@@ -672,7 +683,10 @@ femh_solve_opts opts_with_defaults(const femh_solve_opts* o) {
   // COCG-Jacobi's iteration count grows with the box size in wavelengths:
   // a 6.4-wavelength serving box (64^3) already needs 48 000 in FP64
   if (r.max_iter <= 0) r.max_iter = 200000;
-  if (r.precond_block == 0) r.precond_block = 64;
+  // one block is one wavefront's sequential chain: 16-node blocks give
+  // enough chains to fill the device and take about as many iterations as
+  // 64-node ones
+  if (r.precond_block == 0) r.precond_block = 16;
   // complex64 recurrences can only shrink their residual about one decade
   // before its rounding dominates; an FP64 recurrence with a complex64 matrix
   // can go much further between reliable updates

@@ -185,11 +185,12 @@ struct Stepper {
       // update and direction update run with D = I; z comes from the factor
       FEMH_TRY(ensure_bic(P, o.precond_block));
       partials_c = dev(8 * kPartialSlots);
-      bic_stage = (double*)dev(32 * (size_t)P->bic.nblk + 256);
+      const size_t stage_bytes = 8 * k::bic_stage_doubles(P->bic.nblk) + 256;
+      bic_stage = (double*)dev(stage_bytes);
       if (!partials_c || !bic_stage) return oom();
-      bic_ticket = reinterpret_cast<uint32_t*>(bic_stage + 4 * (size_t)P->bic.nblk);
+      bic_ticket = reinterpret_cast<uint32_t*>(bic_stage + k::bic_stage_doubles(P->bic.nblk));
       FEMH_TRY_HIP(hipMemsetAsync(partials_c, 0, 8 * kPartialSlots, s));
-      FEMH_TRY_HIP(hipMemsetAsync(bic_stage, 0, 32 * (size_t)P->bic.nblk + 256, s));
+      FEMH_TRY_HIP(hipMemsetAsync(bic_stage, 0, stage_bytes, s));
     }
     if (o.precond == FEMH_PRECOND_NONE || bic) {
       if (mixed) {

@@ -144,6 +144,7 @@ SIGNATURES = {
     "femh_export_rhs": (C.c_int, [P, I32, C.POINTER(femh_plane_wave), P]),
     "femh_export_jacobi": (C.c_int, [P, P]),
     "femh_export_bic0": (C.c_int, [P, I32, C.POINTER(I64), P, P, P]),
+    "femh_bic0_apply_dev": (C.c_int, [P, I32, P, P, I32, PD]),
     "femh_spmv_dev": (C.c_int, [P, I32, P, P, I32, PD]),
     "femh_spmm_dev": (C.c_int, [P, I32, I32, P, P, I32, PD]),
     "femh_spmm_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
@@ -544,7 +545,7 @@ class Problem:
         check(self.lib.femh_export_jacobi(self.handle, d.ctypes.data))
         return d
 
-    def export_bic0(self, nodes_per_block=64):
+    def export_bic0(self, nodes_per_block=16):
         """The block incomplete Cholesky factor L (scalar CSR: row_ptr, col,
         vals; columns ascending, diagonal last) for blocks of nodes_per_block
         nodes, built on the device if needed."""
@@ -556,6 +557,18 @@ class Problem:
         check(self.lib.femh_export_bic0(self.handle, nodes_per_block, C.byref(nnz), row_ptr.ctypes.data,
                                         col.ctypes.data, vals.ctypes.data))
         return row_ptr, col, vals
+
+    def bic0_apply_dev(self, r, z, nodes_per_block=16, reps=1):
+        """z = (L L^T)^-1 r with the block incomplete Cholesky factor (device
+        complex128 tensors [n_unknowns]); returns the mean kernel seconds."""
+        import torch
+
+        check_device_tensor(r, torch.complex128, self.n_unknowns, self.ctx.device, "bic0_apply_dev r")
+        check_device_tensor(z, torch.complex128, self.n_unknowns, self.ctx.device, "bic0_apply_dev z")
+        t = C.c_double()
+        check(self.lib.femh_bic0_apply_dev(self.handle, nodes_per_block, r.data_ptr(), z.data_ptr(), reps,
+                                           C.byref(t)))
+        return t.value
 
     def spmv_dev(self, x, y, precision=FEMH_FP64, reps=1):
         dt = _vector_dtype(precision)

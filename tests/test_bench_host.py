@@ -92,3 +92,16 @@ def test_unknown_serving_mode_is_refused():
     import pytest
     with pytest.raises(SystemExit):
         bench.serving_leg(None, None, None, 1, 10, 12, 1, [0.5], ["no_such_mode"])
+
+
+def test_bic_apply_bytes_counts_each_array():
+    """One block of two nodes whose L is the full 6 x 6 lower triangle (21
+    entries, so U holds the 15 below-diagonal ones transposed): every array
+    the application touches, counted by hand."""
+    n = 6
+    factor = (21 + 15) * (16 + 4)          # values and columns of L and U
+    row_starts = 2 * (n + 1) * 4           # lrp and urp
+    dinv = 2 * n * 16                      # 1 / l_uu, staged in both sweeps
+    vectors = 2 * n * 16 + n * 16          # r twice, z once
+    sums = 4 * 8 * 2                       # the block's four sums, written and read back
+    assert bench.bic_apply_bytes(n, 21, 6) == factor + row_starts + dinv + vectors + sums
