@@ -136,7 +136,7 @@ typedef struct {
   int32_t precond;       /* femh_precond; default Jacobi */
   double rtol;           /* stop at ||b - A x||_2 <= rtol ||b||_2 (FP64 true residual); default 1e-6 */
   int32_t max_iter;      /* Krylov iterations in total (inner ones for MIXED); default 200000 */
-  int32_t precond_block; /* FEMH_PRECOND_BIC0: nodes per block, 1..512; default 16 (ignored otherwise) */
+  int32_t precond_block; /* FEMH_PRECOND_BIC0: nodes per block, 1..512; default 4 (ignored otherwise) */
   double inner_rtol;     /* MIXED*: residual reduction between reliable updates; default 0.1
                             (FEMH_MIXED), 1e-3 (FEMH_MIXED_MATRIX) */
   int32_t max_outer;     /* MIXED: refinement steps; default 20 */

@@ -446,15 +446,17 @@ int ensure_bic(Problem* P, int32_t nodes_per_block) {
   double2* uval = (double2*)take(16 * (size_t)nnz_u);
   if (!ucol || !uval) return oom();
   FEMH_TRY_HIP(k::bic_upper(s, n, rpb, lrp, lcol, lval, nullptr, urp, ucol, uval));
-  // the application stages rows in chunks of at least the longest row; 768
-  // entries (about 64 rows of a 64-node block) keep its LDS near 20 KB
+  // the application stages rows in chunks of at least the longest row, and
+  // of about ten entries per row of a block (a row has 9 on average), up to
+  // 768 (64 rows of a 64-node block): small blocks then take little LDS and
+  // more of them run at once on a compute unit
   std::vector<int32_t> hl((size_t)n + 1), hu((size_t)n + 1);
   FEMH_TRY_HIP(hipMemcpyAsync(hl.data(), lrp, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
   FEMH_TRY_HIP(hipMemcpyAsync(hu.data(), urp, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
   FEMH_TRY_HIP(hipStreamSynchronize(s));
   int32_t longest = 0;
   for (int64_t u = 0; u < n; ++u) longest = std::max(longest, std::max(hl[u + 1] - hl[u], hu[u + 1] - hu[u]));
-  P->bic.chunk_cap = std::max(longest, 768);
+  P->bic.chunk_cap = std::max(longest, std::min(768, 10 * rpb));
   P->bic.n = n;
   P->bic.rows_per_block = rpb;
   P->bic.nblk = nblk;
@@ -683,10 +685,10 @@ femh_solve_opts opts_with_defaults(const femh_solve_opts* o) {
   // COCG-Jacobi's iteration count grows with the box size in wavelengths:
   // a 6.4-wavelength serving box (64^3) already needs 48 000 in FP64
   if (r.max_iter <= 0) r.max_iter = 200000;
-  // one block is one wavefront's sequential chain: 16-node blocks give
-  // enough chains to fill the device and take about as many iterations as
-  // 64-node ones
-  if (r.precond_block == 0) r.precond_block = 16;
+  // one block is one wavefront's sequential chain: 4-node blocks give
+  // enough chains to fill the device and took no more iterations than
+  // larger ones on the workloads measured
+  if (r.precond_block == 0) r.precond_block = 4;
   // complex64 recurrences can only shrink their residual about one decade
   // before its rounding dominates; an FP64 recurrence with a complex64 matrix
   // can go much further between reliable updates

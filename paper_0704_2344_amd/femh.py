@@ -545,7 +545,7 @@ class Problem:
         check(self.lib.femh_export_jacobi(self.handle, d.ctypes.data))
         return d
 
-    def export_bic0(self, nodes_per_block=16):
+    def export_bic0(self, nodes_per_block=4):
         """The block incomplete Cholesky factor L (scalar CSR: row_ptr, col,
         vals; columns ascending, diagonal last) for blocks of nodes_per_block
         nodes, built on the device if needed."""
@@ -558,7 +558,7 @@ class Problem:
                                         col.ctypes.data, vals.ctypes.data))
         return row_ptr, col, vals
 
-    def bic0_apply_dev(self, r, z, nodes_per_block=16, reps=1):
+    def bic0_apply_dev(self, r, z, nodes_per_block=4, reps=1):
         """z = (L L^T)^-1 r with the block incomplete Cholesky factor (device
         complex128 tensors [n_unknowns]); returns the mean kernel seconds."""
         import torch

@@ -263,11 +263,11 @@ def test_options_are_checked(ctx, torch):
     with pytest.raises(F.FemhError) as e:
         P.solve_dev(waves + waves, out, batched=True, **BIC)
     assert e.value.status == F.FEMH_E_INVALID
-    # precond_block 0 selects 16 nodes
+    # precond_block 0 selects 4 nodes
     H0, s0, st0 = P.solve(waves, rtol=1e-9, **BIC)
-    H16, s16, st16 = P.solve(waves, rtol=1e-9, precond_block=16, **BIC)
-    assert st0 == st16 == F.FEMH_OK
-    np.testing.assert_array_equal(H0, H16)
+    H4, s4, st4 = P.solve(waves, rtol=1e-9, precond_block=4, **BIC)
+    assert st0 == st4 == F.FEMH_OK
+    np.testing.assert_array_equal(H0, H4)
     P.close()
     # a batching server refuses it for requests of several waves, takes it for one
     srv = F.Server(ctx, max_slots=4, batch_rhs=True)
@@ -305,7 +305,7 @@ def test_served_bic0_requests_match_plain_solves(ctx):
 
 
 def test_pec_cube_30_converges_with_bic0(ctx):
-    """The 30^3 PEC cube (87 186 unknowns; 1 817 blocks of 16 nodes, the
+    """The 30^3 PEC cube (87 186 unknowns; 7 266 blocks of 4 nodes, the
     default, and 455 of 64) to 1e-8; the reported residual is checked
     against the oracle's residual of the returned iterate."""
     prob, waves = W.pec_cube(30)
@@ -319,5 +319,5 @@ def test_pec_cube_30_converges_with_bic0(ctx):
         res = solve.residual(A, H[0][active].reshape(-1), b)
         assert res <= 1.01e-8, (nodes, res, stats)
         assert abs(res - stats[0]["rel_residual"]) <= 1e-10
-        print(f"pec_cube_30 BIC(0) B={nodes or 16}: {stats[0]['iters']} iterations, {stats[0]['seconds']:.3f} s")
+        print(f"pec_cube_30 BIC(0) B={nodes or 4}: {stats[0]['iters']} iterations, {stats[0]['seconds']:.3f} s")
     P.close()
