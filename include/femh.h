@@ -121,6 +121,13 @@ typedef struct {
   double k0;                   /* free-space wavenumber, > 0 */
   double penalty_s;            /* grad-div penalty weight s >= 0 (eq. (2) gives none); 0 selects 1 */
   int32_t arrays_on_device;    /* 1: eps_r, mu_r, pec are device pointers, 0: host pointers */
+  int32_t penalty_surface;     /* 0 (default): the penalty's surface integral of eq. (4) is dropped, and the matrix
+                                  is complex-symmetric by construction.  1: that integral is assembled as printed,
+                                  -s int (W . n)(div H) dS over the ABC outer faces and the faces between active
+                                  and PEC elements, and the matrix is then averaged with its transpose as section
+                                  3.1.4 does (A + (S + S^T) / 2; the right-hand side unchanged).  The paper-literal
+                                  variant, for comparison: it no longer reproduces the incident wave in an empty
+                                  box.  Not combined with symmetry or antisymmetry faces (FEMH_E_INVALID). */
 } femh_problem_desc;
 
 /* Incident plane wave H_i(r) = p exp(-j k0 d . r): |d| = 1, p . d = 0

@@ -47,6 +47,7 @@ struct MeshDev {
   int abc_mask;              // bit f set = outer face f carries the ABC
   int sym_mask;              // bit f set = outer face f is a symmetry plane (n . H = 0)
   int anti_mask;             // bit f set = outer face f is an antisymmetry plane (n x H = 0)
+  int penalty_surface;       // 1: add the printed penalty surface term, averaged with its transpose
   const double2* eps;        // [ne] or null (= 1)
   const double2* mu;         // [ne] or null (= 1)
   const uint8_t* pec;        // [ne] or null (= none)

@@ -274,6 +274,44 @@ __global__ void __launch_bounds__(256) k_assemble(MeshDev m, PatternDev p, int32
             if (i == j) v = cadd(v, mass);
             K[i][j] = cadd(K[i][j], v);
           }
+        // The printed penalty surface term (paper-literal variant), averaged
+        // with its transpose: on each face of the element that lies on an
+        // ABC outer face or against a PEC element, with outward normal along
+        // axis ax (sign sg), the term's row (a, ax) holds
+        // -s sg int N_a dN_b/dx_j dS in column (b, j); its transpose adds
+        // -s sg int N_b dN_a/dx_i dS at (a, i), (b, ax).  Half of each.
+        if (m.penalty_surface) {
+#pragma unroll
+          for (int f = 0; f < 6; ++f) {
+            const int ax = f >> 1, side = f & 1;
+            const int nbr = ee[ax] + (side ? 1 : -1);
+            bool on;
+            if (nbr < 0 || nbr >= nel[ax]) {
+              on = (m.abc_mask >> f) & 1;
+            } else {
+              int en[3] = {ee[0], ee[1], ee[2]};
+              en[ax] = nbr;
+              on = m.pec && m.pec[en[0] + (int64_t)m.nx * (en[1] + (int64_t)m.ny * en[2])];
+            }
+            if (!on) continue;
+            const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
+            const double c = -0.5 * m.s * (side ? 1.0 : -1.0);
+            // int_face N_p dN_q/dx_j dS for the face's nodes p (on the face)
+            auto face_int = [&](const int (&lp)[3], const int (&lq)[3], int j) -> double {
+              if (lp[ax] != side) return 0.0;
+              if (j == ax) return (lq[ax] ? 1.0 : -1.0) / m.h[ax] * m1(lp[t1], lq[t1], m.h[t1]) *
+                                  m1(lp[t2], lq[t2], m.h[t2]);
+              if (lq[ax] != side) return 0.0;
+              const int o = j == t1 ? t2 : t1;
+              return g1(lq[j]) * m1(lp[o], lq[o], m.h[o]);
+            };
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              K[ax][j].x += c * face_int(la, lb, j);
+              K[j][ax].x += c * face_int(lb, la, j);
+            }
+          }
+        }
         // ABC quads of this element containing both nodes
         if (m.abc_mask) {
 #pragma unroll

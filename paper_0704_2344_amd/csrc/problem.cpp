@@ -106,6 +106,16 @@ int validate_desc(const femh_problem_desc* d, std::string& msg) {
       msg = "outer_face entries must be FEMH_FACE_ABC, _NATURAL, _SYM or _ANTISYM";
       return FEMH_E_INVALID;
     }
+  if (d->penalty_surface != 0 && d->penalty_surface != 1) {
+    msg = "penalty_surface must be 0 or 1";
+    return FEMH_E_INVALID;
+  }
+  if (d->penalty_surface)
+    for (int f = 0; f < 6; ++f)
+      if (d->outer_face[f] == FEMH_FACE_SYM || d->outer_face[f] == FEMH_FACE_ANTISYM) {
+        msg = "penalty_surface is not combined with symmetry or antisymmetry faces";
+        return FEMH_E_INVALID;
+      }
   if (d->arrays_on_device != 0 && d->arrays_on_device != 1) {
     msg = "arrays_on_device must be 0 or 1";
     return FEMH_E_INVALID;
@@ -354,6 +364,7 @@ static void fill_mesh(MeshDev& m, const femh_problem_desc* d) {
   m.k0 = d->k0;
   m.s = d->penalty_s == 0.0 ? 1.0 : d->penalty_s;
   m.abc_mask = m.sym_mask = m.anti_mask = 0;
+  m.penalty_surface = d->penalty_surface;
   for (int f = 0; f < 6; ++f) {
     if (d->outer_face[f] == FEMH_FACE_ABC) m.abc_mask |= 1 << f;
     if (d->outer_face[f] == FEMH_FACE_SYM) m.sym_mask |= 1 << f;

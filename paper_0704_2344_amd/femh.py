@@ -68,7 +68,7 @@ class femh_problem_desc(C.Structure):
                 ("h", C.c_double * 3), ("origin", C.c_double * 3),
                 ("eps_r", C.c_void_p), ("mu_r", C.c_void_p), ("pec", C.c_void_p),
                 ("outer_face", C.c_int32 * 6), ("k0", C.c_double), ("penalty_s", C.c_double),
-                ("arrays_on_device", C.c_int32)]
+                ("arrays_on_device", C.c_int32), ("penalty_surface", C.c_int32)]
 
 
 class femh_plane_wave(C.Structure):
@@ -246,11 +246,14 @@ class _Keep:
         return x
 
 
-def make_desc(prob, device_arrays: Optional[dict] = None, keep: Optional[_Keep] = None) -> femh_problem_desc:
+def make_desc(prob, device_arrays: Optional[dict] = None, keep: Optional[_Keep] = None,
+              penalty_surface: int = 0) -> femh_problem_desc:
     """femh_problem_desc from a workloads.Problem.  With device_arrays
     ({"eps_r": tensor, "mu_r": tensor, "pec": tensor}) the descriptor points
-    at device memory instead of the problem's host arrays."""
+    at device memory instead of the problem's host arrays; penalty_surface = 1
+    asks for the printed penalty surface term averaged with its transpose."""
     d = femh_problem_desc()
+    d.penalty_surface = penalty_surface
     d.nx, d.ny, d.nz = prob.nx, prob.ny, prob.nz
     for a in range(3):
         d.h[a] = prob.h[a]
@@ -410,12 +413,12 @@ class Context:
 class Problem:
     """An assembled problem resident on the device."""
 
-    def __init__(self, ctx: Context, prob, device_arrays: Optional[dict] = None):
+    def __init__(self, ctx: Context, prob, device_arrays: Optional[dict] = None, penalty_surface: int = 0):
         self.ctx = ctx
         self.lib = ctx.lib
         self.spec = prob
         keep = _Keep()
-        desc = make_desc(prob, device_arrays, keep)
+        desc = make_desc(prob, device_arrays, keep, penalty_surface)
         h = C.c_void_p()
         check(self.lib.femh_problem_create(ctx.handle, C.byref(desc), C.byref(h)))
         self.handle = h
