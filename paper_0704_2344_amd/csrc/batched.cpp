@@ -526,6 +526,17 @@ int solve_batched(Problem* P, int nrhs, const double2* b, double2* x, const femh
       if (s != FEMH_OK && status == FEMH_OK) status = s;
     }
     for (int col = 0; col < nrhs; ++col) st[col].seconds = ms * 1e-3;
+    if (log_level() >= 1) {
+      int lo = st[0].iters, hi = st[0].iters;
+      double worst = 0.0;
+      for (int col = 0; col < nrhs; ++col) {
+        lo = std::min(lo, st[col].iters);
+        hi = std::max(hi, st[col].iters);
+        worst = std::max(worst, st[col].rel_residual);
+      }
+      logf(1, "batched: %d columns in %zu group(s), %d-%d iterations, worst relative residual %.3e, %.3f s, status %d",
+           nrhs, groups.size(), lo, hi, worst, ms * 1e-3, status);
+    }
   }
   for (BatchStepper* S : groups) delete S;
   if (rc != FEMH_OK) return rc;

@@ -18,6 +18,15 @@ namespace femh {
 void set_error(const char* fmt, ...);
 void clear_error();
 
+// ------------------------------------------------------------------ log
+// FEMH_LOG (environment, read once): 1 logs problem and factor builds, the
+// end of every solve segment (recursive and true residual, the action
+// taken) and the server's admissions; 2 also logs each chunk of iterations
+// as its scalars are read back (a residual history at chunk granularity).
+// Lines go to stderr, prefixed "[femh]".
+int log_level();
+void logf(int level, const char* fmt, ...);
+
 #define FEMH_TRY_HIP(call)                                                                   \
   do {                                                                                       \
     hipError_t e_ = (call);                                                                  \

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -24,6 +25,24 @@ void set_error(const char* fmt, ...) {
 }
 void clear_error() { g_err.clear(); }
 const char* last_error() { return g_err.c_str(); }
+
+int log_level() {
+  static const int level = [] {
+    const char* v = std::getenv("FEMH_LOG");
+    return v ? std::atoi(v) : 0;
+  }();
+  return level;
+}
+
+void logf(int level, const char* fmt, ...) {
+  if (log_level() < level) return;
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[femh] %s\n", buf);
+}
 
 void* Ctx::dmalloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
@@ -480,6 +499,8 @@ int ensure_bic(Problem* P, int32_t nodes_per_block) {
   P->bic.ldinv = ldinv;
   P->bic_nodes = nodes_per_block;
   P->bic_nnz_l = nnz_l;
+  logf(1, "block incomplete Cholesky: %d-node blocks, %d blocks, %lld entries in L, staging chunk %d entries",
+       nodes_per_block, nblk, (long long)nnz_l, P->bic.chunk_cap);
   return FEMH_OK;
 }
 
@@ -597,6 +618,9 @@ int problem_create(Ctx* ctx, const femh_problem_desc* d, Problem** out) {
   P->spmv = k::spmv_launch_for(nn, ctx->n_cu);
 #undef FEMH_ALLOC
 #undef FEMH_HIP_OR_FAIL
+  logf(1, "problem %dx%dx%d: %d active nodes, %lld unknowns, %lld blocks, %.1f MB on the device%s", d->nx, d->ny,
+       d->nz, nn, 3LL * nn, (long long)nnzb, P->dev_bytes / 1e6,
+       d->penalty_surface ? ", printed penalty surface term" : "");
   *out = P;
   return FEMH_OK;
 }
@@ -685,6 +709,7 @@ int problem_import(Ctx* ctx, int64_t nb, int64_t nnzb, const int32_t* row_ptr, c
   P->pat.col_idx = P->col_idx;
   P->grid_nodes = 0;
   P->spmv = k::spmv_launch_for(nn, ctx->n_cu);
+  logf(1, "imported matrix: %d block rows, %lld blocks", nn, (long long)nnzb);
   *out = P;
   return FEMH_OK;
 }

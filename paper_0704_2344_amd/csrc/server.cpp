@@ -189,6 +189,9 @@ void femh_server::admit_locked(std::vector<Request*>& admitted) {
       running.push_back(r);
       admitted.push_back(r);
       it = queue.erase(it);
+      femh::logf(1, "server: request %llu admitted (%dx%dx%d, %d waves, %.1f MB of %.1f MB resident)",
+                 (unsigned long long)r->ticket, r->desc.nx, r->desc.ny, r->desc.nz, (int)r->waves.size(),
+                 r->est_bytes / 1e6, resident / 1e6);
     } else {
       ++it;
     }
@@ -298,6 +301,8 @@ void femh_server::retire(Request* r, int status) {
   r->status = status;
   r->state = Request::FINISHED;
   r->t_done = now_s();
+  femh::logf(1, "server: request %llu finished with status %d, %.3f s after admission", (unsigned long long)r->ticket,
+             status, r->t_done - r->t_start);
   resident -= r->est_bytes;
   running.erase(std::remove(running.begin(), running.end(), r), running.end());
   if (status == FEMH_E_CANCELLED) {

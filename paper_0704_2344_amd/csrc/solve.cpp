@@ -328,6 +328,16 @@ struct Stepper {
     }
   }
 
+  const char* mode_name() const {
+    if (mixed) return "complex64 vectors and matrix";
+    if (m32) return "complex64 matrix, FP64 vectors";
+    return bic ? "FP64, block incomplete Cholesky" : "FP64";
+  }
+  // recursive residual of a scalar block relative to ||b||
+  double rec_rel(const CocgScalars& st) const {
+    return std::sqrt(st.rr * (mixed ? scale * scale : 1.0) / bb);
+  }
+
   // ---- phases
   int start() {
     FEMH_TRY_HIP(hipMemsetAsync(aux, 0, sizeof(Aux), s));
@@ -360,6 +370,7 @@ struct Stepper {
       else FEMH_TRY_HIP(k::cocg_init_c128(s, n, r64, dinv64, x, r64, p64, sc, partials, 0, par()));
     }
     new_segment(0);
+    logf(1, "solve: %lld unknowns, %s, rtol %.1e, ||b|| = %.3e", (long long)n, mode_name(), o.rtol, std::sqrt(bb));
     return FEMH_OK;
   }
 
@@ -367,6 +378,9 @@ struct Stepper {
   int on_stop(const CocgScalars& st) {
     last_done = st.done;
     iters = st.iters_out;
+    static const char* why[] = {"running", "converged", "iteration limit", "breakdown", "residual fell by inner_rtol"};
+    logf(1, "solve: segment stopped at iteration %d (%s), recursive |r|/|b| = %.3e", iters,
+         st.done >= 0 && st.done <= 4 ? why[st.done] : "?", rec_rel(st));
     collect_profile(st.iters_out);
     if (mixed) FEMH_TRY_HIP(k::ir_fold(s, n, x32, scale, x));
     FEMH_TRY(queue_residual());
@@ -377,6 +391,7 @@ struct Stepper {
   int on_check() {
     rel = std::sqrt(ha->rr / bb);
     ++outer;
+    logf(1, "solve: true |b - Ax|/|b| = %.3e after %d iterations", rel, iters);
     if (rel <= o.rtol) return finish(FEMH_OK);
     if (last_done == 2 || iters >= o.max_iter || !std::isfinite(rel)) return finish(FEMH_E_NOT_CONVERGED);
     const int cap = (mixed || m32) ? std::max(o.max_outer, 1) * 50 : std::max(o.max_outer, 1);
@@ -415,6 +430,8 @@ struct Stepper {
   int finish(int st) {
     status = st;
     phase = DONE;
+    logf(1, "solve: finished with status %d after %d iterations, %d checks, relative residual %.3e", st, iters,
+         outer, rel);
     return FEMH_OK;
   }
 
@@ -446,6 +463,7 @@ struct Stepper {
         head ^= 1;
         --inflight;
         *progress = true;
+        if (!stale) logf(2, "solve:   iteration %d, recursive |r|/|b| = %.3e", st.iters_out, rec_rel(st));
         if (!stale && st.done) {
           stop_state = st;
           stale = true;
