@@ -36,6 +36,7 @@
 #include <mutex>
 #include <thread>
 
+#include "admission.h"
 #include "internal.h"
 
 namespace {
@@ -177,25 +178,27 @@ void femh_server::admit_locked(std::vector<Request*>& admitted) {
       ++it;
     }
   }
-  int window = 0;
-  for (auto it = queue.begin(); it != queue.end() && window < 16; ++window) {
-    if ((int)running.size() >= max_slots) break;
-    Request* r = *it;
-    if (resident + r->est_bytes <= budget) {
-      resident += r->est_bytes;
-      peak = std::max(peak, resident);
-      r->state = Request::RUNNING;
-      r->t_start = now_s();
-      running.push_back(r);
-      admitted.push_back(r);
-      it = queue.erase(it);
-      femh::logf(1, "server: request %llu admitted (%dx%dx%d, %d waves, %.1f MB of %.1f MB resident)",
-                 (unsigned long long)r->ticket, r->desc.nx, r->desc.ny, r->desc.nz, (int)r->waves.size(),
-                 r->est_bytes / 1e6, resident / 1e6);
-    } else {
-      ++it;
-    }
+  std::vector<int64_t> bytes;
+  bytes.reserve(queue.size());
+  for (Request* r : queue) bytes.push_back(r->est_bytes);
+  const int64_t before = resident;
+  const std::vector<int> take = femh::plan_admissions(bytes, resident, budget, (int)running.size(), max_slots);
+  int64_t sum = before;
+  std::vector<Request*> taken;
+  for (int i : take) {
+    Request* r = queue[(size_t)i];
+    sum += r->est_bytes;
+    peak = std::max(peak, sum);
+    r->state = Request::RUNNING;
+    r->t_start = now_s();
+    running.push_back(r);
+    admitted.push_back(r);
+    taken.push_back(r);
+    femh::logf(1, "server: request %llu admitted (%dx%dx%d, %d waves, %.1f MB of %.1f MB resident)",
+               (unsigned long long)r->ticket, r->desc.nx, r->desc.ny, r->desc.nz, (int)r->waves.size(),
+               r->est_bytes / 1e6, sum / 1e6);
   }
+  for (Request* r : taken) queue.erase(std::find(queue.begin(), queue.end(), r));
 }
 
 int femh_server::setup(Request* r) {

@@ -1,13 +1,18 @@
 // Host-code checks run under AddressSanitizer and UndefinedBehaviorSanitizer
-// (built by test_host_sanitizers.py with the library's host code only): the
+// (built by test_host_sanitizers.py, the library's host side sanitized): the
 // descriptor and wave validation, the footprint estimate, the refusals of
-// NULL handles, and context creation where no usable device exists.  Every
-// case prints one line; the run fails on the first unexpected status.
+// NULL handles, context creation where no usable device exists, and the
+// server's admission pass driven by a fake executor (simulated arrivals and
+// completions, no device).  Every case prints one line; the run fails if
+// any status or invariant is unexpected.
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <vector>
 
+#include "admission.h"
 #include "femh.h"
 
 static int failures = 0;
@@ -28,7 +33,98 @@ static femh_problem_desc box(int n, const femh_c128* eps, const uint8_t* pec) {
   return d;
 }
 
+// The server's admission pass under a fake executor: requests of random
+// size (1-40 units against a budget of 100) and service time arrive over
+// time; at every arrival and completion the waiting queue is offered to
+// plan_admissions.  Checked after every pass: the resident bytes stay within
+// the budget, at most max_slots run, only the first 16 waiting requests are
+// considered, every request passed over before an admitted one did not fit
+// (or the slots were full) at its turn, and at the end every request has run.
+static void fake_executor() {
+  const int64_t budget = 100;
+  const int max_slots = 6, count = 400;
+  uint64_t seed = 12345;
+  auto rnd = [&](int lo, int hi) {
+    seed = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+    return lo + (int)((seed >> 33) % (uint64_t)(hi - lo + 1));
+  };
+  struct Req {
+    int64_t bytes;
+    double arrive, service, start = -1.0, done = -1.0;
+  };
+  std::vector<Req> req;
+  double t = 0.0;
+  for (int i = 0; i < count; ++i) {
+    t += rnd(0, 20) * 0.1;
+    req.push_back(Req{rnd(1, 40), t, rnd(1, 60) * 0.1});
+  }
+  std::vector<int> queue, running;
+  int64_t resident = 0, peak = 0;
+  int next = 0, bad = 0, passes = 0, skipped_ahead = 0;
+  double now = 0.0;
+  while (next < count || !queue.empty() || !running.empty()) {
+    // next event: an arrival or the earliest completion
+    double t_arr = next < count ? req[next].arrive : 1e300, t_done = 1e300;
+    int who = -1;
+    for (int r : running)
+      if (req[r].done < t_done) t_done = req[r].done, who = r;
+    if (t_arr <= t_done) {
+      now = t_arr;
+      queue.push_back(next++);
+    } else {
+      now = t_done;
+      resident -= req[who].bytes;
+      running.erase(std::find(running.begin(), running.end(), who));
+    }
+    std::vector<int64_t> bytes;
+    for (int r : queue) bytes.push_back(req[r].bytes);
+    const int64_t before = resident;
+    const std::vector<int> take = femh::plan_admissions(bytes, resident, budget, (int)running.size(), max_slots);
+    ++passes;
+    // replay the pass: each position up to the last admitted one was either
+    // admitted or did not fit when its turn came
+    int64_t res = before;
+    int run = (int)running.size();
+    size_t k = 0;
+    const int last = take.empty() ? -1 : take.back();
+    for (int i = 0; i <= last; ++i) {
+      if (k < take.size() && take[k] == i) {
+        if (i >= 16 || run >= max_slots || res + bytes[i] > budget) ++bad;
+        res += bytes[i];
+        ++run;
+        ++k;
+      } else {
+        if (res + bytes[i] <= budget && run < max_slots) ++bad;
+        ++skipped_ahead;
+      }
+    }
+    if (res != resident || resident > budget || run > max_slots) ++bad;
+    peak = std::max(peak, resident);
+    std::vector<int> left;
+    for (size_t i = 0, j = 0; i < queue.size(); ++i) {
+      if (j < take.size() && take[j] == (int)i) {
+        const int r = queue[i];
+        req[r].start = now;
+        req[r].done = now + req[r].service;
+        running.push_back(r);
+        ++j;
+      } else {
+        left.push_back(queue[i]);
+      }
+    }
+    queue.swap(left);
+  }
+  int unrun = 0;
+  for (const Req& r : req)
+    if (r.start < r.arrive || r.done < r.start) ++unrun;
+  std::printf("fake executor: %d requests, %d passes, peak %lld of %lld resident, %d passed over\n", count, passes,
+              (long long)peak, (long long)budget, skipped_ahead);
+  expect("admission invariants held", bad, 0);
+  expect("every request ran", unrun, 0);
+}
+
 int main() {
+  fake_executor();
   const int n = 5, ne = n * n * n;
   std::vector<femh_c128> eps((size_t)ne, femh_c128{2.0, -0.1});
   std::vector<uint8_t> pec((size_t)ne, 0);
