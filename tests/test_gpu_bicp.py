@@ -215,6 +215,27 @@ def test_rows_longer_than_a_wavefront(ctx, torch):
     P.close()
 
 
+def test_iteration_limit_and_chunk_sizes(ctx):
+    """The limit stops the preconditioned recurrence at exactly max_iter
+    iterations (FEMH_E_NOT_CONVERGED), and the solution does not depend on
+    how many iterations are queued between host reads (bit for bit)."""
+    prob, waves = CASES["free_cube_6"]
+    P = F.Problem(ctx, prob)
+    _, stats, st = P.solve(waves, rtol=1e-12, max_iter=5, check_every=2, **BIC)
+    assert st == F.FEMH_E_NOT_CONVERGED
+    assert stats[0]["iters"] == 5 and stats[0]["status"] == F.FEMH_E_NOT_CONVERGED
+    ref = None
+    for every in (1, 7, 32):
+        H, stats, st = P.solve(waves, rtol=1e-9, check_every=every, **BIC)
+        assert st == F.FEMH_OK
+        if ref is None:
+            ref = (H, stats[0]["iters"])
+        else:
+            np.testing.assert_array_equal(H, ref[0])
+            assert stats[0]["iters"] == ref[1]
+    P.close()
+
+
 def test_imported_oracle_matrix_with_bic0(ctx, torch):
     prob, waves = CASES["sphere_shell_14"]
     A = fem.assemble(prob)
