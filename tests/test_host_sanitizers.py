@@ -1,10 +1,11 @@
 """The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer
 (CPU): every source is compiled with the sanitizers on its host side only
 (the gfx950 device code is built as usual, without them), linked with
-host_sanitized_checks.cpp, and run.  The driver
-exercises descriptor and wave validation, the footprint estimate, the NULL
-refusals and context creation without a usable device; the test fails on
-any unexpected status or any sanitizer report."""
+host_sanitized_checks.cpp, and run.  That program exercises descriptor and
+wave validation, the footprint estimate, the NULL refusals, context
+creation without a usable device and the server's admission pass under a
+fake executor; the test fails on any unexpected status or any sanitizer
+report."""
 import os
 import shutil
 import subprocess
@@ -36,7 +37,7 @@ def test_host_code_is_clean_under_sanitizers(tmp_path):
     for p in procs:
         out, _ = p.communicate()
         assert p.returncode == 0, out
-    drv = str(tmp_path / "driver.o")
+    drv = str(tmp_path / "checks.o")
     r = subprocess.run([CLANG] + common + ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-c",
                         os.path.join(ROOT, "tests", "host_sanitized_checks.cpp"), "-o", drv],
                        capture_output=True, text=True)
