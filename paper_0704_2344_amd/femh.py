@@ -625,9 +625,9 @@ class Server:
         ctx.children.add(self)
         _live_children.add(self)
 
-    def submit(self, prob, waves, **opt_kw) -> int:
+    def submit(self, prob, waves, penalty_surface: int = 0, **opt_kw) -> int:
         keep = _Keep()
-        desc = make_desc(prob, None, keep)
+        desc = make_desc(prob, None, keep, penalty_surface)
         w = make_waves(waves)
         o = make_opts(**opt_kw)
         t = C.c_uint64()

@@ -106,3 +106,26 @@ def test_options_are_checked(ctx):
         F.Problem(ctx, q, penalty_surface=1)
     assert e.value.status == F.FEMH_E_INVALID
     assert "penalty_surface" in F.last_error()
+
+
+def test_served_request_with_the_term_matches_a_plain_solve(ctx):
+    """The flag travels with the descriptor through the server: a served
+    request with the printed term gives the plain solve's field bit for bit,
+    and differs from the same request without it."""
+    prob = CASES["sphere_shell_10"]
+    rng = np.random.default_rng(4)
+    waves = [W.random_wave(rng) for _ in range(2)]
+    P = F.Problem(ctx, prob, penalty_surface=1)
+    Hp, sp_, stp = P.solve(waves, precision=F.FEMH_FP64, rtol=1e-9)
+    assert stp == F.FEMH_OK
+    P.close()
+    srv = F.Server(ctx, max_slots=4)
+    t1 = srv.submit(prob, waves, penalty_surface=1, precision=F.FEMH_FP64, rtol=1e-9)
+    t0 = srv.submit(prob, waves, precision=F.FEMH_FP64, rtol=1e-9)
+    st1, H1, s1 = srv.poll(t1, len(waves), Hp.shape)
+    st0, H0, _ = srv.poll(t0, len(waves), Hp.shape)
+    assert st1 == F.FEMH_OK and st0 == F.FEMH_OK
+    np.testing.assert_array_equal(H1, Hp)
+    assert [s["iters"] for s in s1] == [s["iters"] for s in sp_]
+    assert np.abs(H1 - H0).max() > 1e-3 * np.abs(H0).max()
+    srv.close()
