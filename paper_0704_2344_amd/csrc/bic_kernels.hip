@@ -392,15 +392,26 @@ __global__ void __launch_bounds__(kSumThreads) k_bic_sum(int32_t nblk, int32_t p
 }
 
 // Segment start after an application z = M^-1 r whose totals are in
-// sums[0..3]: p = z; workgroup 0 records rho = r^T z, ||r||^2 and the start
-// verdict (converged / breakdown) in slot par.
+// sums[0..3]: p = z; the last workgroup to finish its copy records
+// rho = r^T z, ||r||^2 and the start verdict (converged / breakdown) in slot
+// par.  Every workgroup reads the stop flag at entry, before it takes its
+// ticket, so the flag is written only after all of those reads.
 __global__ void __launch_bounds__(256) k_bic_init(int64_t n, const double2* __restrict__ zin,
                                                   double2* __restrict__ p, CocgScalars* sc,
                                                   const double* __restrict__ sums, int par) {
   if (sc->done) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = zin[i];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(&sc->ticket[1], 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    __threadfence();
+    sc->ticket[1] = 0u;  // ready for the next launch (the kernel boundary orders it)
     const double2 rho = make_double2(sums[0], sums[1]);
     const double rr = sums[2], zz = sums[3];
     sc->rho[par] = rho;
