@@ -36,6 +36,19 @@ constexpr size_t kScratchBytes = kScratchPartials + 65536;
 static_assert(sizeof(femh::BatchScalars) <= 65536, "scalar block exceeds its scratch slot");
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
+// A pair of timing events, destroyed on every return path.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t create() {
+    const hipError_t e = hipEventCreate(&a);
+    return e != hipSuccess ? e : hipEventCreate(&b);
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
 struct DevTmp {
   Ctx* c;
   void* p;
@@ -390,20 +403,17 @@ int femh_spmm_dev(femh_problem* p, int32_t precision, int32_t ncols, const void*
   FEMH_TRY_HIP(hipMemcpyAsync(scd.p, hs, sizeof(*hs), hipMemcpyHostToDevice, s));
   FEMH_TRY_HIP(hipStreamSynchronize(s));
   FEMH_TRY(femh::autotune_spmm(p, val64, Xd, Yd, (double*)part.p, (const femh::BatchScalars*)scd.p));
-  hipEvent_t e0, e1;
-  FEMH_TRY_HIP(hipEventCreate(&e0));
-  FEMH_TRY_HIP(hipEventCreate(&e1));
-  FEMH_TRY_HIP(hipEventRecord(e0, s));
+  EventPair ev;
+  FEMH_TRY_HIP(ev.create());
+  FEMH_TRY_HIP(hipEventRecord(ev.a, s));
   for (int i = 0; i < reps; ++i)
     FEMH_TRY_HIP(femh::k::bspmm(s, p->pat, p->val32, val64, Xd, Yd, (double*)part.p,
                                 (const femh::BatchScalars*)scd.p, p->tile));
-  FEMH_TRY_HIP(hipEventRecord(e1, s));
-  FEMH_TRY_HIP(hipEventSynchronize(e1));
+  FEMH_TRY_HIP(hipEventRecord(ev.b, s));
+  FEMH_TRY_HIP(hipEventSynchronize(ev.b));
   float ms = 0;
-  FEMH_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+  FEMH_TRY_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
   if (avg_seconds) *avg_seconds = ms * 1e-3 / reps;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (!direct)
     FEMH_TRY_HIP(hipMemcpy2DAsync(Y, (size_t)ncols * 16, yp.p, 64 * 16, (size_t)ncols * 16, (size_t)n,
                                   hipMemcpyDeviceToDevice, s));
@@ -569,19 +579,16 @@ int femh_bic0_apply_dev(femh_problem* p, int32_t nodes_per_block, const femh_c12
   double* st = (double*)stage.p;
   uint32_t* ticket = reinterpret_cast<uint32_t*>(st + femh::k::bic_stage_doubles(p->bic.nblk));
   FEMH_TRY_HIP(hipMemsetAsync(stage.p, 0, stage_bytes, c->stream));
-  hipEvent_t e0, e1;
-  FEMH_TRY_HIP(hipEventCreate(&e0));
-  FEMH_TRY_HIP(hipEventCreate(&e1));
-  FEMH_TRY_HIP(hipEventRecord(e0, c->stream));
+  EventPair ev;
+  FEMH_TRY_HIP(ev.create());
+  FEMH_TRY_HIP(hipEventRecord(ev.a, c->stream));
   for (int i = 0; i < reps; ++i)
     FEMH_TRY_HIP(femh::k::bic_apply(c->stream, p->bic, (const double2*)r, (double2*)z, st, ticket, (double*)out.p,
                                     nullptr));
-  FEMH_TRY_HIP(hipEventRecord(e1, c->stream));
-  FEMH_TRY_HIP(hipEventSynchronize(e1));
+  FEMH_TRY_HIP(hipEventRecord(ev.b, c->stream));
+  FEMH_TRY_HIP(hipEventSynchronize(ev.b));
   float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  (void)hipEventElapsedTime(&ms, ev.a, ev.b);
   if (avg_seconds) *avg_seconds = ms * 1e-3 / reps;
   return FEMH_OK;
 }
@@ -594,10 +601,10 @@ int femh_spmv_dev(femh_problem* p, int32_t precision, const void* x, void* y, in
     return FEMH_E_INVALID;
   }
   Ctx* c = p->ctx;
-  hipEvent_t e0, e1;
-  FEMH_TRY_HIP(hipEventCreate(&e0));
-  FEMH_TRY_HIP(hipEventCreate(&e1));
-  FEMH_TRY_HIP(hipEventRecord(e0, c->stream));
+  FEMH_TRY_HIP(hipSetDevice(c->device));
+  EventPair ev;
+  FEMH_TRY_HIP(ev.create());
+  FEMH_TRY_HIP(hipEventRecord(ev.a, c->stream));
   for (int i = 0; i < reps; ++i) {
     if (precision == FEMH_FP64)
       FEMH_TRY_HIP(femh::k::spmv_c128(c->stream, p->pat, p->val64, (const double2*)x, (double2*)y, p->spmv));
@@ -606,13 +613,11 @@ int femh_spmv_dev(femh_problem* p, int32_t precision, const void* x, void* y, in
     else
       FEMH_TRY_HIP(femh::k::spmv_c64(c->stream, p->pat, p->val32, (const float2*)x, (float2*)y, p->spmv));
   }
-  FEMH_TRY_HIP(hipEventRecord(e1, c->stream));
-  FEMH_TRY_HIP(hipEventSynchronize(e1));
+  FEMH_TRY_HIP(hipEventRecord(ev.b, c->stream));
+  FEMH_TRY_HIP(hipEventSynchronize(ev.b));
   float ms = 0;
-  FEMH_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+  FEMH_TRY_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
   if (avg_seconds) *avg_seconds = ms * 1e-3 / reps;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   return FEMH_OK;
 }
 
@@ -662,22 +667,20 @@ int femh_spmv_half_dev(femh_problem* p, const void* x, void* y, int32_t reps, do
     femh::set_error("bad spmv arguments");
     return FEMH_E_INVALID;
   }
+  FEMH_TRY_HIP(hipSetDevice(p->ctx->device));
   FEMH_TRY(femh::ensure_half_store(p));
   Ctx* c = p->ctx;
-  hipEvent_t e0, e1;
-  FEMH_TRY_HIP(hipEventCreate(&e0));
-  FEMH_TRY_HIP(hipEventCreate(&e1));
-  FEMH_TRY_HIP(hipEventRecord(e0, c->stream));
+  EventPair ev;
+  FEMH_TRY_HIP(ev.create());
+  FEMH_TRY_HIP(hipEventRecord(ev.a, c->stream));
   for (int i = 0; i < reps; ++i)
     FEMH_TRY_HIP(femh::k::spmv_half_c128(c->stream, p->pat, p->hval64, p->hpos, (const double2*)x, (double2*)y,
                                          p->spmv));
-  FEMH_TRY_HIP(hipEventRecord(e1, c->stream));
-  FEMH_TRY_HIP(hipEventSynchronize(e1));
+  FEMH_TRY_HIP(hipEventRecord(ev.b, c->stream));
+  FEMH_TRY_HIP(hipEventSynchronize(ev.b));
   float ms = 0;
-  FEMH_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+  FEMH_TRY_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
   if (avg_seconds) *avg_seconds = ms * 1e-3 / reps;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   return FEMH_OK;
 }
 
@@ -688,6 +691,7 @@ int femh_bw_probe(femh_ctx* c, int64_t bytes, int32_t reps, double* gbps) {
     return FEMH_E_INVALID;
   }
   bytes &= ~(int64_t)15;
+  FEMH_TRY_HIP(hipSetDevice(c->device));
   DevTmp a(c, bytes), b(c, bytes);
   if (!a.p || !b.p) {
     femh::set_error("device allocation failed (probe)");
@@ -695,18 +699,15 @@ int femh_bw_probe(femh_ctx* c, int64_t bytes, int32_t reps, double* gbps) {
   }
   FEMH_TRY_HIP(hipMemsetAsync(a.p, 0, bytes, c->stream));
   FEMH_TRY_HIP(femh::k::copy_probe(c->stream, (const float4*)a.p, (float4*)b.p, bytes / 16));
-  hipEvent_t e0, e1;
-  FEMH_TRY_HIP(hipEventCreate(&e0));
-  FEMH_TRY_HIP(hipEventCreate(&e1));
-  FEMH_TRY_HIP(hipEventRecord(e0, c->stream));
+  EventPair ev;
+  FEMH_TRY_HIP(ev.create());
+  FEMH_TRY_HIP(hipEventRecord(ev.a, c->stream));
   for (int i = 0; i < reps; ++i) FEMH_TRY_HIP(femh::k::copy_probe(c->stream, (const float4*)a.p, (float4*)b.p, bytes / 16));
-  FEMH_TRY_HIP(hipEventRecord(e1, c->stream));
-  FEMH_TRY_HIP(hipEventSynchronize(e1));
+  FEMH_TRY_HIP(hipEventRecord(ev.b, c->stream));
+  FEMH_TRY_HIP(hipEventSynchronize(ev.b));
   float ms = 0;
-  FEMH_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+  FEMH_TRY_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
   *gbps = 2.0 * (double)bytes / (ms * 1e-3 / reps) / 1e9;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   return FEMH_OK;
 }
 

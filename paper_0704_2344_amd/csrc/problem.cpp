@@ -425,6 +425,12 @@ int ensure_bic(Problem* P, int32_t nodes_per_block) {
     return FEMH_E_INVALID;
   }
   if (P->bic_nodes == nodes_per_block) return FEMH_OK;
+  // the factor's row starts are 32-bit: bound its entries by A's scalar count
+  if (P->pat.nnzb * 9 > (int64_t)INT32_MAX) {
+    set_error("block incomplete Cholesky: %lld stored blocks exceed the factor's 32-bit row starts",
+              (long long)P->pat.nnzb);
+    return FEMH_E_INVALID;
+  }
   drop_bic(P);
   Ctx* c = P->ctx;
   hipStream_t s = c->stream;
