@@ -299,8 +299,10 @@ int femh_export_jacobi(const femh_problem* prob, femh_c128* dinv);
  * the diagonal entry last.  *nnz receives the entry count; with row_ptr,
  * col_idx and vals all NULL only the count is returned (call once to size
  * the buffers, then again to fill them).  Host pointers.  Errors:
- * FEMH_E_INVALID (nodes_per_block outside 1..512, NULL prob or nnz),
- * FEMH_E_BREAKDOWN (a pivot vanished or is not finite), FEMH_E_OOM. */
+ * FEMH_E_INVALID (nodes_per_block outside 1..512, NULL prob or nnz, or
+ * more than 2^31 - 1 scalar entries in A, the range of the factor's 32-bit
+ * row starts), FEMH_E_BREAKDOWN (a pivot vanished or is not finite),
+ * FEMH_E_OOM. */
 int femh_export_bic0(femh_problem* prob, int32_t nodes_per_block, int64_t* nnz, int32_t* row_ptr, int32_t* col_idx,
                      femh_c128* vals);
 
