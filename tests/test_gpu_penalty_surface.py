@@ -9,6 +9,7 @@ its transpose as section 3.1.4 does.
              <= 1e-9 (rtol from the oracle's condition number)
   empty box  the solution is no longer the incident wave (the oracle
              measures 90 % at 10^3; reading A3's matrix 4.8 %)
+  forms      batched FP64 and complex64-matrix solves against the same LU
   options    penalty_surface outside {0, 1}, or with plane faces, refused
 """
 import numpy as np
@@ -92,6 +93,34 @@ def test_empty_box_solution_against_the_oracle_and_the_incident_wave(ctx):
     assert err_a3 < 0.06 and err_lit > 0.5
     P.close()
     P0.close()
+
+
+@pytest.mark.parametrize("prec,batched", [(F.FEMH_FP64, True), (F.FEMH_MIXED_MATRIX, False),
+                                          (F.FEMH_MIXED_MATRIX, True)])
+def test_other_solver_forms_with_the_term_match_lu(ctx, prec, batched):
+    """The printed term through the batched solver and the complex64-matrix
+    form: every wave's field against the oracle's sparse LU of
+    A + (S + S^T) / 2 to the target (1e-9 FP64, 1e-6 complex64 matrix), the
+    solve tolerance taken from the oracle's condition estimate so that the
+    target is certified."""
+    import torch
+    prob = CASES["random_pec_partial_abc"]
+    rng = np.random.default_rng(8)
+    waves = [W.random_wave(rng) for _ in range(3)]
+    M = _literal(prob)
+    X = solve.sparse_solve(M, fem.rhs(prob, waves))
+    kappa = solve.condest(M)
+    target = 1e-9 if prec == F.FEMH_FP64 else 1e-6
+    P = F.Problem(ctx, prob, penalty_surface=1)
+    out = torch.zeros(P.grid_shape(len(waves)), dtype=torch.complex128, device="cuda")
+    stats, st = P.solve_dev(waves, out, batched=batched, precision=prec, rtol=min(1e-7, 0.1 * target / kappa))
+    assert st == F.FEMH_OK, stats
+    H = out.cpu().numpy()
+    Ho = fem.scatter_to_grid(prob, X)
+    for r in range(len(waves)):
+        err = np.linalg.norm(H[r] - Ho[r]) / np.linalg.norm(Ho[r])
+        assert err <= target, (prec, batched, r, err, stats[r])
+    P.close()
 
 
 def test_options_are_checked(ctx):
